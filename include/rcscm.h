@@ -1,0 +1,204 @@
+/*
+ * rcscm.h - C ABI of the MI355X (gfx950) library for rank-constrained
+ * spatial covariance matrix (SCM) estimation (Kubo, Takamune, Kitamura,
+ * Saruwatari, APSIPA 2019).
+ *
+ * Model (Sec. II-B-1, eqs. (2)-(10)): per frequency i and frame j,
+ *     x_ij ~ N_c(0, r^h_ij a_i a_i^H + r^u_ij (R'_i + lambda_i b_i b_i^H)),
+ * with a_i (target steering vector), R'_i (rank-(M-1) Hermitian PSD SCM of the
+ * diffuse noise) and b_i (unit null vector of R'_i) fixed.  The library
+ * estimates theta = {r^h_ij, r^u_ij, lambda_i} by the MAP-EM iteration of
+ * Sec. II-B-2 and extracts the target with the multichannel Wiener filter.
+ *
+ * Two update rules are provided:
+ *   RCSCM_RULE_ACCEL - the second-stage accelerated rule (Algorithm 2,
+ *                      eqs. (46)-(56)): scalar work per bin, one reduction
+ *                      over frames per frequency for lambda_i.
+ *   RCSCM_RULE_NAIVE - the literal E-step/M-step (eqs. (13)-(20)) with an
+ *                      M x M factorisation of the model covariance per bin.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller, unless stated
+ *     otherwise.  Complex arrays are interleaved (re, im).
+ *   - Work is enqueued on the stream given at create (a hipStream_t passed as
+ *     void*; NULL = the legacy default stream).  Only rcscm_sync,
+ *     rcscm_objective and rcscm_last_status block the host.
+ *   - Errors are returned as rcscm_status; nothing throws across the ABI.
+ *     Argument errors are detected on the host before any device work.
+ *     Data errors found by kernels (non-null b, non-PSD R', non-finite x or
+ *     state) are recorded per row on the device and returned by the next
+ *     rcscm_sync.  rcscm_last_error() describes the most recent failure.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Batched (ragged) layout, used by rcscm_create_batch: U utterances, each
+ * with I frequencies, J_u frames and M_u microphones.  Per-utterance arrays
+ * are concatenated in utterance order without padding:
+ *   x      complex64  sum_u I*J_u*M_u     (utterance u: [I][J_u][M_u])
+ *   a, b   complex128 sum_u I*M_u         ([I][M_u])
+ *   Rp     complex128 sum_u I*M_u*M_u     ([I][M_u][M_u])
+ *   rh, ru, s_hat     sum_u I*J_u         ([I][J_u])
+ *   lam    float      U*I                 ([U][I])
+ * A single utterance (rcscm_create) is the case U = 1.
+ */
+#ifndef RCSCM_H
+#define RCSCM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RCSCM_MAX_M 8      /* microphones per utterance: 2 <= M <= 8 */
+#define RCSCM_VERSION 1
+
+typedef struct rcscm_ctx rcscm_ctx; /* opaque; created and freed by the library */
+
+typedef enum {
+  RCSCM_OK = 0,
+  RCSCM_EINVAL = -1,     /* bad scalar argument or NULL pointer                 */
+  RCSCM_ESHAPE = -2,     /* bad I, J, M, U or K                                 */
+  RCSCM_ENOTNULL = -3,   /* ||R'b|| > 1e-6 ||R'||_F for some row (b is not null) */
+  RCSCM_ENOTPSD = -4,    /* R' + b b^H not positive definite (rank of R' < M-1) */
+  RCSCM_ENONFINITE = -5, /* non-finite x, state, or a non-positive lambda        */
+  RCSCM_EDEVICE = -6,    /* a HIP runtime call failed                            */
+  RCSCM_ENOMEM = -7,     /* device allocation failed                             */
+  RCSCM_ESTATE = -8      /* call out of order (e.g. iterate before init)         */
+} rcscm_status;
+
+typedef enum { RCSCM_RULE_NAIVE = 0, RCSCM_RULE_ACCEL = 1 } rcscm_rule;
+
+/* How the K-iteration loop of the accelerated rule is executed.
+ *   STREAM:   one pass over HBM per iteration (K+1 launches, the lambda
+ *             reduction of iteration k is finished by launch k+1); rows are
+ *             split into fixed-size chunks.  Works for any J.
+ *   RESIDENT: one workgroup owns a frequency row for all K iterations and
+ *             keeps its per-bin data in registers (one launch per
+ *             bins-per-lane class).  Needs J_u <= 16384.
+ *   AUTO:     RESIDENT when every row fits, else STREAM.                  */
+typedef enum { RCSCM_SCHED_AUTO = 0, RCSCM_SCHED_STREAM = 1, RCSCM_SCHED_RESIDENT = 2 } rcscm_sched;
+
+/* How the per-frequency sum over frames for lambda (eqs. (18), (43), (55)) is
+ * accumulated.  F64: per-lane and cross-lane sums in double.  KAHAN32:
+ * Kahan-compensated float per lane, then a compensated (TwoSum) float tree. */
+typedef enum { RCSCM_LAMSUM_F64 = 0, RCSCM_LAMSUM_KAHAN32 = 1 } rcscm_lamsum;
+
+#define RCSCM_FLAG_GRAPH       1u  /* capture the STREAM K loop in a hipGraph      */
+#define RCSCM_FLAG_CHECKPOINT  2u  /* keep theta_k per iteration for rcscm_backward */
+
+typedef struct {
+  double alpha;    /* inverse-gamma shape; default 1.1 (Table 2); needs alpha+2 > 0 */
+  double beta;     /* inverse-gamma scale; default 1e-16 (Table 2); needs beta >= 0 */
+  float rh0;       /* initial r^h used when rcscm_init gets rh0 == NULL; default 1   */
+  float ru0;       /* initial r^u used when ru0 == NULL; default 1                   */
+  float lam0;      /* initial lambda used when lam0 == NULL; default 1               */
+  int rule;        /* rcscm_rule; default RCSCM_RULE_ACCEL                           */
+  int schedule;    /* rcscm_sched; default RCSCM_SCHED_AUTO                          */
+  int lamsum;      /* rcscm_lamsum; default RCSCM_LAMSUM_F64                         */
+  int block;       /* threads per workgroup of the RESIDENT kernel: 0 (auto), 64,
+                      128, 256, 512 or 1024                                          */
+  int chunk;       /* bins per workgroup of the STREAM kernel: 0 (auto) or a
+                      multiple of 256 in [256, 8192]                                  */
+  unsigned flags;  /* RCSCM_FLAG_* */
+} rcscm_params;
+
+/* Fills *p with the defaults above. */
+void rcscm_default_params(rcscm_params* p);
+
+/* Single utterance: I frequencies, J frames, M microphones.  Allocates the
+ * device workspace (see rcscm_workspace_bytes) on the current HIP device.
+ * params may be NULL (defaults).  Errors: EINVAL (alpha+2 <= 0, beta < 0,
+ * non-positive or non-finite inits, bad rule/schedule/block/chunk), ESHAPE
+ * (I < 1, J < 1, M < 2 or M > RCSCM_MAX_M), ENOMEM, EDEVICE.  On error *out
+ * is set to NULL and nothing is allocated. */
+rcscm_status rcscm_create(rcscm_ctx** out, int I, int J, int M, const rcscm_params* params,
+                          void* stream);
+
+/* Ragged batch of U utterances sharing I; J[u], M[u] are HOST arrays of
+ * length U.  Same errors as rcscm_create, per utterance. */
+rcscm_status rcscm_create_batch(rcscm_ctx** out, int U, int I, const int* J, const int* M,
+                                const rcscm_params* params, void* stream);
+
+/* Per-frequency setup and per-bin precomputation (Algorithm 2, before the
+ * loop; eqs. (32), (33), (46)-(48) and the pseudoinverse of eq. (26)):
+ *   - b is normalised and R' projected onto the orthogonal complement of b,
+ *     in FP64; (R')^+ = (R' + b b^H)^{-1} - b b^H from an FP64 Cholesky
+ *     factor C C^H = R' + b b^H;
+ *   - per bin, in FP64 from the complex64 x, then stored as float:
+ *     tau^(ax) = a^H (R')^+ x, sigma^(bx) = b^H x and
+ *     nu = tau^(xx) - |tau^(ax)|^2 / tau^(aa) >= 0 (as a sum of squares).
+ * x: complex64 batch layout; a, Rp, b: complex128 batch layout.
+ * rh0, ru0: float batch layout [..][I][J_u] or NULL (use params->rh0/ru0);
+ * lam0: float [U][I] or NULL (params->lam0).  All are read during this call's
+ * stream work only; the ACCEL rule keeps no reference to x afterwards.  The
+ * NAIVE rule re-reads x in every iteration: x must stay valid and unchanged
+ * until the context is destroyed.  Data errors (ENOTNULL, ENOTPSD, ENONFINITE)
+ * surface at the next rcscm_sync. */
+rcscm_status rcscm_init(rcscm_ctx* ctx, const void* x, const void* a, const void* Rp,
+                        const void* b, const float* rh0, const float* ru0, const float* lam0);
+
+/* Runs K >= 0 further EM iterations from the current state (eqs. (13)-(20)
+ * for NAIVE; Algorithm 2 for ACCEL).  Within an iteration r^h and lambda use
+ * the values at its start; r^u uses the new lambda.  iterate(K1) followed by
+ * iterate(K2) gives the same state as iterate(K1+K2) for a fixed schedule.
+ * Asynchronous.  Errors: ESTATE before init, ESHAPE for K < 0. */
+rcscm_status rcscm_iterate(rcscm_ctx* ctx, int K);
+
+/* Copies the current state into rh, ru (batch layout [..][I][J_u]) and lam
+ * ([U][I]) and, if s_hat != NULL, writes the Wiener-filter estimate of the
+ * dry target s_hat_ij = r^h a^H Sigma^{-1} x = gamma_ij rho^(ax)_ij with
+ * gamma_ij = r^h_ij / (r^u_ij + r^h_ij rho^(aa)_i) at the current state
+ * (complex64, batch layout).  Any output pointer may be NULL.  Async. */
+rcscm_status rcscm_extract(rcscm_ctx* ctx, float* rh, float* ru, float* lam, void* s_hat);
+
+/* Replaces the state (device arrays in batch layout; none may be NULL).
+ * Async.  Used to resume from a saved state. */
+rcscm_status rcscm_set_state(rcscm_ctx* ctx, const float* rh, const float* ru, const float* lam);
+
+/* Waits for the context's stream and returns the first data error recorded
+ * by a kernel since init (see rcscm_status), or OK. */
+rcscm_status rcscm_sync(rcscm_ctx* ctx);
+
+/* Negative log-posterior of the current state (the objective the MAP-EM
+ * iteration cannot increase; Sec. II-B), summed over all bins, evaluated in
+ * FP64 on the device from the FP32 per-bin terms:
+ *   sum_ij [ M log pi + M log r^u + log lambda + log pdet(R') +
+ *            log(1 + r^h rho^(aa) / r^u) + (rho^(xx) - gamma |rho^(ax)|^2) / r^u
+ *            + (alpha + 1) log r^h + beta / r^h ].
+ * *nlp is a HOST pointer.  Blocks. */
+rcscm_status rcscm_objective(rcscm_ctx* ctx, double* nlp);
+
+/* Reverse-mode gradient of L = sum_ij |s_hat_ij - s_target_ij|^2 through the
+ * last rcscm_iterate(K) call of a context created with RCSCM_FLAG_CHECKPOINT
+ * (ACCEL rule), the extraction and the per-bin precomputation.
+ * x: the complex64 input given to init (read again; must be unchanged).
+ * grad_s_hat: complex64 dL/dRe(s_hat) + i dL/dIm(s_hat), batch layout.
+ * Outputs (any may be NULL): grad_x complex64 [..][I][J_u][M_u] in the same
+ * convention (dL/dRe x + i dL/dIm x); grad_rh0 float [..][I][J_u];
+ * grad_lam0 float [U][I].  The gradient w.r.t. r^u_0 is not returned.
+ * Errors: ESTATE if the context has no checkpoints or was not iterated. */
+rcscm_status rcscm_backward(rcscm_ctx* ctx, const void* x, const void* grad_s_hat, void* grad_x,
+                            float* grad_rh0, float* grad_lam0);
+
+/* Frees every device buffer of the context (after waiting for its stream). */
+void rcscm_destroy(rcscm_ctx* ctx);
+
+/* Human-readable description of the last failure on ctx (never NULL; ctx may
+ * be NULL for errors from create). */
+const char* rcscm_last_error(const rcscm_ctx* ctx);
+
+/* Bytes of device workspace a context of this shape allocates. */
+size_t rcscm_workspace_bytes(int U, int I, const int* J, const int* M, const rcscm_params* params);
+
+/* Schedule chosen for the RESIDENT / STREAM loop after create (for tests and
+ * the autotuner): writes the schedule, block size and chunk size in use. */
+rcscm_status rcscm_get_schedule(const rcscm_ctx* ctx, int* schedule, int* block, int* chunk);
+
+/* Library version (RCSCM_VERSION). */
+int rcscm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCSCM_H */

@@ -1,0 +1,450 @@
+// Second-stage accelerated EM iteration (Algorithm 2) on gfx950.
+//
+// Two schedules of the same per-bin arithmetic (accel_common.h):
+//
+// RESIDENT: one workgroup per (utterance, frequency) row.  Each lane holds
+//   BPL bins (frames j = lane + q*NT) of the row in registers - tau^ax,
+//   sigma^bx, nu, r^h, r^u - for all K iterations.  Per iteration: phase A
+//   over the lane's bins, the lambda frame sum (wave butterfly, then one LDS
+//   slot per wave, one barrier), phase B.  HBM traffic: 28 bytes read and
+//   8 bytes written per bin for the whole K loop.
+//
+// STREAM: rows are cut into chunks; launch k (k = 1..K+1) finishes iteration
+//   k-1 and starts iteration k.  Finishing iteration k-1 needs lambda_{k-1},
+//   the mean over the whole row, which launch k reads as the per-chunk
+//   partial sums written by launch k-1 - so the frame-sum barrier falls on a
+//   launch boundary and no workgroup ever waits for another.  Phase A of
+//   iteration k-1 is recomputed from the stored state of iteration k-2
+//   (cheap arithmetic) instead of storing its intermediates.  HBM traffic
+//   per launch: 28 bytes read and 8 bytes written per bin.
+#include "accel_common.h"
+
+namespace rcscm {
+
+namespace {
+
+// ---------------------------------------------------------------- RESIDENT --
+
+template <int NT, int BPL, int LS>
+__global__ __launch_bounds__(NT) void accel_resident_kernel(
+    const int* __restrict__ row_list, const RowInfo* __restrict__ rows,
+    const RowConstF* __restrict__ rcf, const float4* __restrict__ tsig,
+    const float* __restrict__ nu, float* __restrict__ rh, float* __restrict__ ru,
+    float* __restrict__ lam, float inv_a2, float beta_a2, int K, float* __restrict__ ck_rh,
+    float* __restrict__ ck_ru, float* __restrict__ ck_lam, long long ck_sb, int ck_sr,
+    unsigned* __restrict__ status) {
+  constexpr int NW = NT / 64;
+  const int row = row_list[blockIdx.x];
+  const RowInfo ri = rows[row];
+  const RowConstF rc = rcf[row];
+  const int J = ri.J;
+  const long long base = ri.bin_off;
+  const int t = threadIdx.x;
+  const int wave = t >> 6;
+  const double invJ = 1.0 / (double)J;
+
+  float4 ts[BPL];
+  float vnu[BPL], vrh[BPL], vru[BPL];
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * NT;
+    if (j < J) {
+      ts[q] = tsig[base + j];
+      vnu[q] = nu[base + j];
+      vrh[q] = rh[base + j];
+      vru[q] = ru[base + j];
+    } else {
+      ts[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      vnu[q] = 0.f;
+      vrh[q] = 1.f;
+      vru[q] = 1.f;
+    }
+  }
+  float lam_t = lam[row];
+  __shared__ uint64_t red[2][NW];
+
+  for (int k = 0; k < K; ++k) {
+    if (ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
+#pragma unroll
+      for (int q = 0; q < BPL; ++q) {
+        const int j = t + q * NT;
+        if (j < J) {
+          ck_rh[(long long)k * ck_sb + base + j] = vrh[q];
+          ck_ru[(long long)k * ck_sb + base + j] = vru[q];
+        }
+      }
+      if (t == 0) ck_lam[(long long)k * ck_sr + row] = lam_t;
+    }
+    const LamTerms Lt = lam_terms(rc, lam_t);
+    LamAcc<LS> acc;
+    PhaseA A[BPL];
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      A[q] = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
+      if (t + q * NT < J) acc.add(A[q].t);
+      vrh[q] = A[q].rh_new;
+    }
+    acc = wave_allreduce<LS>(acc);
+    if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
+    __syncthreads();
+    const float lam_n = wave_sum_packed<LS>(red[k & 1], NW).mean(invJ);
+    const LamTerms Ln = lam_terms(rc, lam_n);
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) vru[q] = phase_b(ts[q], vnu[q], A[q], rc, Ln);
+    lam_t = lam_n;
+  }
+
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * NT;
+    if (j < J) {
+      rh[base + j] = vrh[q];
+      ru[base + j] = vru[q];
+      bad = bad || !isfinite(vrh[q]) || !isfinite(vru[q]);
+    }
+  }
+  if (t == 0) {
+    lam[row] = lam_t;
+    if (!(lam_t > 0.0f) || !isfinite(lam_t)) atomicOr(status + row, ST_LAM_NONPOS);
+  }
+  if (bad) atomicOr(status + row, ST_NONFINITE_STATE);
+}
+
+template <int NT, int BPL, int LS>
+void res_launch(hipStream_t s, int nrows, const int* row_list, const RowInfo* rows,
+                const RowConstF* rcf, const float4* tsig, const float* nu, float* rh, float* ru,
+                float* lam, float inv_a2, float beta_a2, int K, float* ck_rh, float* ck_ru,
+                float* ck_lam, long long ck_sb, int ck_sr, unsigned* status) {
+  hipLaunchKernelGGL((accel_resident_kernel<NT, BPL, LS>), dim3(nrows), dim3(NT), 0, s, row_list,
+                     rows, rcf, tsig, nu, rh, ru, lam, inv_a2, beta_a2, K, ck_rh, ck_ru, ck_lam,
+                     ck_sb, ck_sr, status);
+}
+
+using ResFn = void (*)(hipStream_t, int, const int*, const RowInfo*, const RowConstF*,
+                       const float4*, const float*, float*, float*, float*, float, float, int,
+                       float*, float*, float*, long long, int, unsigned*);
+
+#define RCSCM_RES_BPL_LIST(NT, LS)                                                       \
+  {res_launch<NT, 1, LS>, res_launch<NT, 2, LS>, res_launch<NT, 3, LS>,                  \
+   res_launch<NT, 4, LS>, res_launch<NT, 5, LS>, res_launch<NT, 6, LS>,                  \
+   res_launch<NT, 7, LS>, res_launch<NT, 8, LS>, nullptr, res_launch<NT, 10, LS>,        \
+   nullptr, res_launch<NT, 12, LS>, nullptr, nullptr, nullptr, res_launch<NT, 16, LS>}
+
+// 1024-lane workgroups are limited to 128 VGPRs: 10+ bins per lane would spill.
+#define RCSCM_RES_BPL_LIST_1024(LS)                                                      \
+  {res_launch<1024, 1, LS>, res_launch<1024, 2, LS>, res_launch<1024, 3, LS>,            \
+   res_launch<1024, 4, LS>, res_launch<1024, 5, LS>, res_launch<1024, 6, LS>,            \
+   res_launch<1024, 7, LS>, res_launch<1024, 8, LS>, nullptr, nullptr, nullptr, nullptr, \
+   nullptr, nullptr, nullptr, nullptr}
+
+// [lamsum][nt index][bpl-1]; nt index: 64,128,256,512,1024
+const ResFn kRes[2][5][16] = {
+    {RCSCM_RES_BPL_LIST(64, 0), RCSCM_RES_BPL_LIST(128, 0), RCSCM_RES_BPL_LIST(256, 0),
+     RCSCM_RES_BPL_LIST(512, 0), RCSCM_RES_BPL_LIST_1024(0)},
+    {RCSCM_RES_BPL_LIST(64, 1), RCSCM_RES_BPL_LIST(128, 1), RCSCM_RES_BPL_LIST(256, 1),
+     RCSCM_RES_BPL_LIST(512, 1), RCSCM_RES_BPL_LIST_1024(1)}};
+
+int nt_index(int nt) {
+  switch (nt) {
+    case 64: return 0;
+    case 128: return 1;
+    case 256: return 2;
+    case 512: return 3;
+    case 1024: return 4;
+    default: return -1;
+  }
+}
+
+// ------------------------------------------------------------------ STREAM --
+
+constexpr int kStreamNT = 256;
+
+template <int BPL, int LS, bool FINISH, bool START>
+__global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
+    const ChunkInfo* __restrict__ chunks, const RowInfo* __restrict__ rows,
+    const RowConstF* __restrict__ rcf, const float4* __restrict__ tsig,
+    const float* __restrict__ nu, float* __restrict__ rh, float* __restrict__ ru,
+    const float* __restrict__ lam_prev, float* __restrict__ lam_new,
+    const uint64_t* __restrict__ part_in, uint64_t* __restrict__ part_out, float inv_a2,
+    float beta_a2, unsigned* __restrict__ status) {
+  constexpr int NW = kStreamNT / 64;
+  const ChunkInfo ck = chunks[blockIdx.x];
+  const RowInfo ri = rows[ck.row];
+  const RowConstF rc = rcf[ck.row];
+  const long long base = ri.bin_off + ck.start;
+  const int len = ck.len;
+  const int t = threadIdx.x;
+  const int wave = t >> 6;
+  const double invJ = 1.0 / (double)ri.J;
+  __shared__ uint64_t red[NW];
+
+  float4 ts[BPL];
+  float vrh[BPL], vru[BPL];
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * kStreamNT;
+    if (j < len) {
+      ts[q] = tsig[base + j];
+      vrh[q] = rh[base + j];
+      vru[q] = ru[base + j];
+    } else {
+      ts[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      vrh[q] = 1.f;
+      vru[q] = 1.f;
+    }
+  }
+  float lam_cur = lam_prev[ck.row];
+  if constexpr (FINISH) {
+    // lambda of the iteration being finished: mean of the row's partial sums
+    const float lam_k = wave_sum_packed<LS>(part_in + ri.part_off, ri.nparts).mean(invJ);
+    if (ck.start == 0 && t == 0) {
+      lam_new[ck.row] = lam_k;
+      if (!(lam_k > 0.0f) || !isfinite(lam_k)) atomicOr(status + ck.row, ST_LAM_NONPOS);
+    }
+    const LamTerms Lt = lam_terms(rc, lam_cur);
+    const LamTerms Ln = lam_terms(rc, lam_k);
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      const int j = t + q * kStreamNT;
+      const float vnu = (j < len) ? nu[base + j] : 0.f;
+      const PhaseA A = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
+      vrh[q] = A.rh_new;
+      vru[q] = phase_b(ts[q], vnu, A, rc, Ln);
+      if (j < len) {
+        rh[base + j] = vrh[q];
+        ru[base + j] = vru[q];
+        bad = bad || !isfinite(vrh[q]) || !isfinite(vru[q]);
+      }
+    }
+    if (bad) atomicOr(status + ck.row, ST_NONFINITE_STATE);
+    lam_cur = lam_k;
+  }
+  if constexpr (START) {
+    const LamTerms Lt = lam_terms(rc, lam_cur);
+    LamAcc<LS> acc;
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      const PhaseA A = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
+      if (t + q * kStreamNT < len) acc.add(A.t);
+    }
+    acc = wave_allreduce<LS>(acc);
+    if ((t & 63) == 0) red[wave] = acc.pack();
+    __syncthreads();
+    if (t == 0) {
+      LamAcc<LS> tot;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) tot.combine(LamAcc<LS>::unpack(red[w]));
+      part_out[ck.part] = tot.pack();
+    }
+  }
+}
+
+template <int BPL, int LS, bool F, bool S>
+void stream_launch(hipStream_t s, int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
+                   const RowConstF* rcf, const float4* tsig, const float* nu, float* rh,
+                   float* ru, const float* lam_prev, float* lam_new, const uint64_t* part_in,
+                   uint64_t* part_out, float inv_a2, float beta_a2, unsigned* status) {
+  hipLaunchKernelGGL((accel_stream_kernel<BPL, LS, F, S>), dim3(nchunks), dim3(kStreamNT), 0, s,
+                     chunks, rows, rcf, tsig, nu, rh, ru, lam_prev, lam_new, part_in, part_out,
+                     inv_a2, beta_a2, status);
+}
+
+template <int BPL, int LS>
+void stream_dispatch(hipStream_t s, bool F, bool S, int nchunks, const ChunkInfo* chunks,
+                     const RowInfo* rows, const RowConstF* rcf, const float4* tsig,
+                     const float* nu, float* rh, float* ru, const float* lam_prev,
+                     float* lam_new, const uint64_t* part_in, uint64_t* part_out, float inv_a2,
+                     float beta_a2, unsigned* status) {
+  if (F && S)
+    stream_launch<BPL, LS, true, true>(s, nchunks, chunks, rows, rcf, tsig, nu, rh, ru, lam_prev,
+                                       lam_new, part_in, part_out, inv_a2, beta_a2, status);
+  else if (F)
+    stream_launch<BPL, LS, true, false>(s, nchunks, chunks, rows, rcf, tsig, nu, rh, ru, lam_prev,
+                                        lam_new, part_in, part_out, inv_a2, beta_a2, status);
+  else if (S)
+    stream_launch<BPL, LS, false, true>(s, nchunks, chunks, rows, rcf, tsig, nu, rh, ru, lam_prev,
+                                        lam_new, part_in, part_out, inv_a2, beta_a2, status);
+}
+
+// ----------------------------------------------------------------- EXTRACT --
+
+__global__ __launch_bounds__(256) void extract_kernel(
+    const ChunkInfo* __restrict__ chunks, const RowInfo* __restrict__ rows,
+    const RowConstF* __restrict__ rcf, const float4* __restrict__ tsig,
+    const float* __restrict__ rh_in, const float* __restrict__ ru_in,
+    const float* __restrict__ lam_in, float* __restrict__ rh_out, float* __restrict__ ru_out,
+    float* __restrict__ lam_out, float2* __restrict__ s_hat) {
+  const ChunkInfo ck = chunks[blockIdx.x];
+  const RowInfo ri = rows[ck.row];
+  const RowConstF rc = rcf[ck.row];
+  const float lam = lam_in[ck.row];
+  const LamTerms L = lam_terms(rc, lam);
+  if (lam_out != nullptr && ck.start == 0 && threadIdx.x == 0) lam_out[ck.row] = lam;
+  for (int jj = threadIdx.x; jj < ck.len; jj += blockDim.x) {
+    const long long bin = ri.bin_off + ck.start + jj;
+    const float vrh = rh_in[bin], vru = ru_in[bin];
+    if (rh_out != nullptr) rh_out[bin] = vrh;
+    if (ru_out != nullptr) ru_out[bin] = vru;
+    if (s_hat != nullptr) {
+      const float4 ts = tsig[bin];
+      // s_hat = gamma rho^ax, rho^ax = tau^ax + sigma^ab sigma^bx / lambda
+      const float rx_re = fmaf(L.sp_re, ts.z, fmaf(-L.sp_im, ts.w, ts.x));
+      const float rx_im = fmaf(L.sp_re, ts.w, fmaf(L.sp_im, ts.z, ts.y));
+      const float g = vrh / fmaf(vrh, L.rho_aa, vru);
+      s_hat[bin] = make_float2(g * rx_re, g * rx_im);
+    }
+  }
+}
+
+// --------------------------------------------------------------- OBJECTIVE --
+
+__global__ __launch_bounds__(256) void objective_kernel(
+    const ChunkInfo* __restrict__ chunks, const RowInfo* __restrict__ rows,
+    const RowConstF* __restrict__ rcf, const RowConstD* __restrict__ rcd,
+    const float4* __restrict__ tsig, const float* __restrict__ nu, const float* __restrict__ rh,
+    const float* __restrict__ ru, const float* __restrict__ lam, double alpha, double beta,
+    double* __restrict__ partial) {
+  const ChunkInfo ck = chunks[blockIdx.x];
+  const RowInfo ri = rows[ck.row];
+  const double taa = rcd[ck.row].t_aa;
+  const double2 sab = rcd[ck.row].s_ab;
+  const double logpdet = rcd[ck.row].logpdet;
+  const double l = (double)lam[ck.row];
+  const double M = (double)ri.M;
+  const double sab2 = sab.x * sab.x + sab.y * sab.y;
+  const double rho_aa = taa + sab2 / l;
+  const double inv_taa = taa > 0.0 ? 1.0 / taa : 0.0;
+  const double c0 = M * log(3.14159265358979323846) + log(l) + logpdet;
+  double acc = 0.0;
+  for (int jj = threadIdx.x; jj < ck.len; jj += blockDim.x) {
+    const long long bin = ri.bin_off + ck.start + jj;
+    const float4 ts = tsig[bin];
+    const double h = rh[bin], u = ru[bin];
+    const double tar = ts.x, tai = ts.y, sbr = ts.z, sbi = ts.w;
+    const double txx = (double)nu[bin] + (tar * tar + tai * tai) * inv_taa;
+    const double rax_r = tar + (sab.x * sbr - sab.y * sbi) / l;
+    const double rax_i = tai + (sab.x * sbi + sab.y * sbr) / l;
+    const double rxx = txx + (sbr * sbr + sbi * sbi) / l;
+    const double g = h / (u + h * rho_aa);
+    acc += c0 + M * log(u) + log1p(h * rho_aa / u) + (rxx - g * (rax_r * rax_r + rax_i * rax_i)) / u +
+           (alpha + 1.0) * log(h) + beta / h;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// -------------------------------------------------------------- FILL STATE --
+
+__global__ __launch_bounds__(256) void fill_state_kernel(
+    int nrows, const RowInfo* __restrict__ rows, const float* __restrict__ rh0,
+    const float* __restrict__ ru0, const float* __restrict__ lam0, float rh_c, float ru_c,
+    float lam_c, float* __restrict__ rh, float* __restrict__ ru, float* __restrict__ lam,
+    unsigned* __restrict__ status) {
+  const int row = blockIdx.x;
+  const RowInfo ri = rows[row];
+  bool bad = false;
+  for (int j = threadIdx.x; j < ri.J; j += blockDim.x) {
+    const long long bin = ri.bin_off + j;
+    const float h = rh0 ? rh0[bin] : rh_c;
+    const float u = ru0 ? ru0[bin] : ru_c;
+    rh[bin] = h;
+    ru[bin] = u;
+    bad = bad || !(h > 0.0f) || !(u > 0.0f) || !isfinite(h) || !isfinite(u);
+  }
+  if (threadIdx.x == 0) {
+    const float l = lam0 ? lam0[row] : lam_c;
+    lam[row] = l;
+    if (!(l > 0.0f) || !isfinite(l)) bad = true;
+  }
+  if (bad) atomicOr(status + row, ST_NONFINITE_STATE);
+}
+
+}  // namespace
+
+bool resident_supported(int nt, int bpl) {
+  const int ni = nt_index(nt);
+  return ni >= 0 && bpl >= 1 && bpl <= 16 && kRes[0][ni][bpl - 1] != nullptr;
+}
+
+void launch_accel_resident(hipStream_t s, int nt, int bpl, int lamsum, int nrows,
+                           const int* row_list, const RowInfo* rows, const RowConstF* rcf,
+                           const float4* tsig, const float* nu, float* rh, float* ru, float* lam,
+                           float alpha, float beta, int K, float* ckpt_rh, float* ckpt_ru,
+                           float* ckpt_lam, long long ckpt_stride_bins, int ckpt_stride_rows,
+                           unsigned* status) {
+  if (nrows <= 0 || K <= 0) return;
+  const float inv_a2 = (float)(1.0 / ((double)alpha + 2.0));
+  const float beta_a2 = (float)((double)beta / ((double)alpha + 2.0));
+  kRes[lamsum ? 1 : 0][nt_index(nt)][bpl - 1](s, nrows, row_list, rows, rcf, tsig, nu, rh, ru,
+                                              lam, inv_a2, beta_a2, K, ckpt_rh, ckpt_ru,
+                                              ckpt_lam, ckpt_stride_bins, ckpt_stride_rows,
+                                              status);
+}
+
+void launch_accel_stream(hipStream_t s, int lamsum, bool finish_prev, bool start_next,
+                         int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
+                         const RowConstF* rcf, const float4* tsig, const float* nu, float* rh,
+                         float* ru, const float* lam_prev, float* lam_new,
+                         const uint64_t* part_in, uint64_t* part_out, float alpha, float beta,
+                         int chunk_threads, unsigned* status) {
+  if (nchunks <= 0) return;
+  const float inv_a2 = (float)(1.0 / ((double)alpha + 2.0));
+  const float beta_a2 = (float)((double)beta / ((double)alpha + 2.0));
+  const int bpl = chunk_threads / kStreamNT;
+#define RCSCM_STREAM_CASE(B)                                                                  \
+  case B:                                                                                     \
+    if (lamsum)                                                                               \
+      stream_dispatch<B, 1>(s, finish_prev, start_next, nchunks, chunks, rows, rcf, tsig, nu,  \
+                            rh, ru, lam_prev, lam_new, part_in, part_out, inv_a2, beta_a2,    \
+                            status);                                                          \
+    else                                                                                      \
+      stream_dispatch<B, 0>(s, finish_prev, start_next, nchunks, chunks, rows, rcf, tsig, nu,  \
+                            rh, ru, lam_prev, lam_new, part_in, part_out, inv_a2, beta_a2,    \
+                            status);                                                          \
+    break;
+  switch (bpl) {
+    RCSCM_STREAM_CASE(1)
+    RCSCM_STREAM_CASE(2)
+    RCSCM_STREAM_CASE(4)
+    RCSCM_STREAM_CASE(8)
+    default: break;
+  }
+#undef RCSCM_STREAM_CASE
+}
+
+void launch_extract(hipStream_t s, int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
+                    const RowConstF* rcf, const float4* tsig, const float* rh_in,
+                    const float* ru_in, const float* lam_in, float* rh_out, float* ru_out,
+                    float* lam_out, float2* s_hat, unsigned* status) {
+  (void)status;
+  if (nchunks <= 0) return;
+  hipLaunchKernelGGL(extract_kernel, dim3(nchunks), dim3(256), 0, s, chunks, rows, rcf, tsig,
+                     rh_in, ru_in, lam_in, rh_out, ru_out, lam_out, s_hat);
+}
+
+void launch_objective(hipStream_t s, int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
+                      const RowConstF* rcf, const RowConstD* rcd, const float4* tsig,
+                      const float* nu, const float* rh, const float* ru, const float* lam,
+                      double alpha, double beta, double* partial) {
+  if (nchunks <= 0) return;
+  hipLaunchKernelGGL(objective_kernel, dim3(nchunks), dim3(256), 0, s, chunks, rows, rcf, rcd,
+                     tsig, nu, rh, ru, lam, alpha, beta, partial);
+}
+
+void launch_fill_state(hipStream_t s, int nrows, const RowInfo* rows, const float* rh0,
+                       const float* ru0, const float* lam0, float rh_c, float ru_c, float lam_c,
+                       float* rh, float* ru, float* lam, unsigned* status) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(fill_state_kernel, dim3(nrows), dim3(256), 0, s, nrows, rows, rh0, ru0, lam0,
+                     rh_c, ru_c, lam_c, rh, ru, lam, status);
+}
+
+}  // namespace rcscm

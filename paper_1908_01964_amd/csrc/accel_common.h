@@ -1,0 +1,174 @@
+// Device helpers of the second-stage accelerated iteration (Algorithm 2).
+//
+// Per bin, with the values at the start of the iteration (tilde) and the
+// per-row constants tau^aa, sigma^ab:
+//   rho~ax = tau^ax + sigma^ab sigma^bx / lambda~                 eq. (52)
+//   gamma~ = r~h / (r~u + r~h rho~aa),  rho~aa = tau^aa + |sigma^ab|^2/lambda~  eqs. (34), (50)
+//   r^h    = (gamma~ (r~u + gamma~ |rho~ax|^2) + beta) / (alpha + 2)            eq. (54)
+//   e      = sigma^bx - gamma~ conj(sigma^ab) rho~ax
+//   t      = gamma~ |sigma^ab|^2 + |e|^2 / r~u   (lambda <- mean_j t)          eq. (55)
+// and, after the frame sum has produced the new lambda,
+//   r^u    = (1/M) [ gamma~ r~u rho^aa + nu + |tau^ax - w tau^aa|^2 / tau^aa
+//                    + |e|^2 / lambda ],       w = gamma~ rho~ax.
+// The last line equals eq. (56): with y = x - w a, the statistic of eq. (44)
+// is U^ = gamma~ r~u a a^H + y y^H, and tr(R^{-1} U^) splits by the
+// pseudoinverse expansion eq. (26) into gamma~ r~u rho^aa + y^H (R')^+ y +
+// |b^H y|^2 / lambda, where b^H y = e and
+// y^H (R')^+ y = nu + |tau^ax - w tau^aa|^2 / tau^aa.  Every term is a
+// non-negative number, so no float cancellation occurs.
+#pragma once
+
+#include "rcscm_internal.h"
+
+namespace rcscm {
+
+__device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
+
+// Per-row quantities that depend on one value of lambda.
+struct LamTerms {
+  float il;      // 1 / lambda
+  float rho_aa;  // tau^aa + |sigma^ab|^2 / lambda
+  float sp_re;   // sigma^ab / lambda
+  float sp_im;
+};
+
+__device__ __forceinline__ LamTerms lam_terms(const RowConstF& rc, float lam) {
+  LamTerms L;
+  L.il = 1.0f / lam;
+  L.rho_aa = fmaf(rc.sab2, L.il, rc.t_aa);
+  L.sp_re = rc.sab_re * L.il;
+  L.sp_im = rc.sab_im * L.il;
+  return L;
+}
+
+// Phase A of one bin: new r^h, the lambda term t, and what phase B needs.
+struct PhaseA {
+  float rh_new, t, cg, w_re, w_im, E;
+};
+
+__device__ __forceinline__ PhaseA phase_a(const float4 ts, float rh, float ru, const RowConstF& rc,
+                                          const LamTerms& Lt, float inv_a2, float beta_a2) {
+  PhaseA o;
+  // rho~ax = tau^ax + (sigma^ab / lambda~) sigma^bx
+  const float rx_re = fmaf(Lt.sp_re, ts.z, fmaf(-Lt.sp_im, ts.w, ts.x));
+  const float rx_im = fmaf(Lt.sp_re, ts.w, fmaf(Lt.sp_im, ts.z, ts.y));
+  const float g = rh * frcp(fmaf(rh, Lt.rho_aa, ru));
+  const float r2 = fmaf(rx_re, rx_re, rx_im * rx_im);
+  o.rh_new = fmaf(g * fmaf(g, r2, ru), inv_a2, beta_a2);
+  o.w_re = g * rx_re;
+  o.w_im = g * rx_im;
+  // e = sigma^bx - conj(sigma^ab) w
+  const float e_re = ts.z - fmaf(rc.sab_re, o.w_re, rc.sab_im * o.w_im);
+  const float e_im = ts.w - fmaf(rc.sab_re, o.w_im, -rc.sab_im * o.w_re);
+  o.E = fmaf(e_re, e_re, e_im * e_im);
+  o.t = fmaf(g, rc.sab2, o.E * frcp(ru));
+  o.cg = g * ru;
+  return o;
+}
+
+// Phase B of one bin: new r^u given the new lambda (terms Ln).
+__device__ __forceinline__ float phase_b(const float4 ts, float nu, const PhaseA& A,
+                                         const RowConstF& rc, const LamTerms& Ln) {
+  const float d_re = fmaf(-A.w_re, rc.t_aa, ts.x);
+  const float d_im = fmaf(-A.w_im, rc.t_aa, ts.y);
+  float acc = fmaf(A.cg, Ln.rho_aa, nu);
+  acc = fmaf(fmaf(d_re, d_re, d_im * d_im), rc.inv_t_aa, acc);
+  acc = fmaf(A.E, Ln.il, acc);
+  return acc * rc.invM;
+}
+
+// ---- frame-sum accumulators for lambda --------------------------------------
+// Policy 0 (F64): double per lane and across lanes.
+// Policy 1 (KAHAN32): Kahan-compensated float per lane; lanes combined with a
+// TwoSum tree.  State (s, c) represents s - c.
+
+template <int LS>
+struct LamAcc;
+
+template <>
+struct LamAcc<0> {
+  double s;
+  __device__ __forceinline__ LamAcc() : s(0.0) {}
+  __device__ __forceinline__ void add(float t) { s += (double)t; }
+  __device__ __forceinline__ void combine(const LamAcc& o) { s += o.s; }
+  __device__ __forceinline__ LamAcc shfl_xor(int off) const {
+    LamAcc r;
+    r.s = __shfl_xor(s, off, 64);
+    return r;
+  }
+  __device__ __forceinline__ LamAcc shfl(int lane) const {
+    LamAcc r;
+    r.s = __shfl(s, lane, 64);
+    return r;
+  }
+  __device__ __forceinline__ uint64_t pack() const { return __double_as_longlong(s); }
+  __device__ __forceinline__ static LamAcc unpack(uint64_t v) {
+    LamAcc r;
+    r.s = __longlong_as_double((long long)v);
+    return r;
+  }
+  __device__ __forceinline__ float mean(double invJ) const { return (float)(s * invJ); }
+};
+
+template <>
+struct LamAcc<1> {
+  float s, c;
+  __device__ __forceinline__ LamAcc() : s(0.0f), c(0.0f) {}
+  __device__ __forceinline__ void add(float t) {
+    const float y = t - c;
+    const float tt = s + y;
+    c = (tt - s) - y;
+    s = tt;
+  }
+  __device__ __forceinline__ void combine(const LamAcc& o) {
+    const float ss = s + o.s;
+    const float bp = ss - s;
+    const float err = (s - (ss - bp)) + (o.s - bp);
+    c = c + o.c - err;
+    s = ss;
+  }
+  __device__ __forceinline__ LamAcc shfl_xor(int off) const {
+    LamAcc r;
+    r.s = __shfl_xor(s, off, 64);
+    r.c = __shfl_xor(c, off, 64);
+    return r;
+  }
+  __device__ __forceinline__ LamAcc shfl(int lane) const {
+    LamAcc r;
+    r.s = __shfl(s, lane, 64);
+    r.c = __shfl(c, lane, 64);
+    return r;
+  }
+  __device__ __forceinline__ uint64_t pack() const {
+    return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)__float_as_uint(s);
+  }
+  __device__ __forceinline__ static LamAcc unpack(uint64_t v) {
+    LamAcc r;
+    r.s = __uint_as_float((unsigned)(v & 0xffffffffu));
+    r.c = __uint_as_float((unsigned)(v >> 32));
+    return r;
+  }
+  __device__ __forceinline__ float mean(double invJ) const {
+    return (float)(((double)s - (double)c) * invJ);
+  }
+};
+
+// Butterfly over the 64 lanes of a wave, then lane 0's value for everyone
+// (the same association order in every wave of every workgroup).
+template <int LS>
+__device__ __forceinline__ LamAcc<LS> wave_allreduce(LamAcc<LS> a) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a.combine(a.shfl_xor(off));
+  return a.shfl(0);
+}
+
+// Sum of n packed accumulators p[0..n), computed identically by every wave.
+template <int LS>
+__device__ __forceinline__ LamAcc<LS> wave_sum_packed(const uint64_t* p, int n) {
+  const int lane = threadIdx.x & 63;
+  LamAcc<LS> a;
+  for (int k = lane; k < n; k += 64) a.combine(LamAcc<LS>::unpack(p[k]));
+  return wave_allreduce<LS>(a);
+}
+
+}  // namespace rcscm

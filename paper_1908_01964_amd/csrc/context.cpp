@@ -1,0 +1,688 @@
+// Host side of the C ABI (include/rcscm.h): argument validation, row and
+// chunk tables, device workspace, schedules, hipGraph capture of the STREAM
+// loop, status collection.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "rcscm.h"
+#include "rcscm_internal.h"
+
+using namespace rcscm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kResBpl[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16};
+constexpr int kMaxResidentJ = 512 * 16;
+
+int round_up_bpl(int need) {
+  for (int b : kResBpl)
+    if (b >= need) return b;
+  return -1;
+}
+
+struct Buffers {
+  std::vector<void*> ptrs;
+  ~Buffers() {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct rcscm_ctx {
+  int U = 0, I = 0;
+  std::vector<int> J, M;
+  rcscm_params p{};
+  hipStream_t stream = nullptr;
+  int nrows = 0;
+  long long nbins = 0;
+  int chunk = 1024;
+  int nchunks = 0;
+  int schedule = RCSCM_SCHED_RESIDENT;
+  int res_nt = 256;
+  std::vector<RowInfo> h_rows;
+  std::vector<ChunkInfo> h_chunks;
+  // chunk ranges per microphone count (chunks sorted by M in d_chunks_m)
+  std::vector<std::pair<int, int>> m_range = std::vector<std::pair<int, int>>(RCSCM_MAX_M + 1, {0, 0});
+  struct ResClass {
+    int bpl, count, offset;
+  };
+  std::vector<ResClass> res_classes;
+
+  Buffers mem;
+  RowInfo* d_rows = nullptr;
+  ChunkInfo* d_chunks = nullptr;
+  ChunkInfo* d_chunks_m = nullptr;
+  int* d_row_list = nullptr;
+  RowConstD* d_rcd = nullptr;
+  RowConstF* d_rcf = nullptr;
+  RowSpatialF* d_rsf = nullptr;
+  float4* d_tsig = nullptr;
+  float* d_nu = nullptr;
+  float* d_rh = nullptr;
+  float* d_ru = nullptr;
+  float* d_lam[2] = {nullptr, nullptr};
+  int lam_cur = 0;
+  uint64_t* d_part[2] = {nullptr, nullptr};
+  unsigned* d_status = nullptr;
+  double* d_objpart = nullptr;
+  float* d_uhat = nullptr;
+  float2* d_rinv = nullptr;
+  const float2* x_borrowed = nullptr;
+  // checkpoints of the last iterate() call
+  float* d_ck_rh = nullptr;
+  float* d_ck_ru = nullptr;
+  float* d_ck_lam = nullptr;
+  int ck_capacity = 0;
+  int ck_K = -1;
+  bool inited = false;
+  std::string err;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+
+  rcscm_status fail(rcscm_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+  template <class T>
+  rcscm_status alloc(T** out, size_t count, const char* what) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(e == hipErrorOutOfMemory ? RCSCM_ENOMEM : RCSCM_EDEVICE,
+                  std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
+    }
+    mem.ptrs.push_back(ptr);
+    *out = static_cast<T*>(ptr);
+    return RCSCM_OK;
+  }
+};
+
+#define RCSCM_HIP(ctx, call)                                                            \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      (void)hipGetLastError();                                                          \
+      return (ctx)->fail(RCSCM_EDEVICE, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    }                                                                                   \
+  } while (0)
+
+#define RCSCM_TRY(expr)            \
+  do {                             \
+    rcscm_status s_ = (expr);      \
+    if (s_ != RCSCM_OK) return s_; \
+  } while (0)
+
+extern "C" {
+
+void rcscm_default_params(rcscm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->alpha = 1.1;
+  p->beta = 1e-16;
+  p->rh0 = 1.0f;
+  p->ru0 = 1.0f;
+  p->lam0 = 1.0f;
+  p->rule = RCSCM_RULE_ACCEL;
+  p->schedule = RCSCM_SCHED_AUTO;
+  p->lamsum = RCSCM_LAMSUM_F64;
+  p->block = 0;
+  p->chunk = 0;
+  p->flags = 0u;
+}
+
+int rcscm_version(void) { return RCSCM_VERSION; }
+
+static rcscm_status validate(int U, int I, const int* J, const int* M, const rcscm_params* p,
+                             std::string* msg) {
+  if (U < 1) {
+    *msg = "U must be >= 1";
+    return RCSCM_ESHAPE;
+  }
+  if (I < 1) {
+    *msg = "I must be >= 1";
+    return RCSCM_ESHAPE;
+  }
+  if (!J || !M) {
+    *msg = "J and M arrays must not be NULL";
+    return RCSCM_EINVAL;
+  }
+  long long bins = 0;
+  for (int u = 0; u < U; ++u) {
+    if (J[u] < 1) {
+      *msg = "J must be >= 1 (utterance " + std::to_string(u) + ")";
+      return RCSCM_ESHAPE;
+    }
+    if (M[u] < 2 || M[u] > RCSCM_MAX_M) {
+      *msg = "M must be in [2, 8] (utterance " + std::to_string(u) + ")";
+      return RCSCM_ESHAPE;
+    }
+    bins += (long long)I * J[u];
+  }
+  if (bins > (1LL << 40)) {
+    *msg = "too many bins";
+    return RCSCM_ESHAPE;
+  }
+  if ((long long)U * I > (1LL << 30)) {
+    *msg = "too many rows";
+    return RCSCM_ESHAPE;
+  }
+  if (!(std::isfinite(p->alpha) && p->alpha + 2.0 > 0.0)) {
+    *msg = "alpha must be finite with alpha + 2 > 0";
+    return RCSCM_EINVAL;
+  }
+  if (!(std::isfinite(p->beta) && p->beta >= 0.0)) {
+    *msg = "beta must be finite and >= 0";
+    return RCSCM_EINVAL;
+  }
+  if (!(std::isfinite(p->rh0) && p->rh0 > 0.0f && std::isfinite(p->ru0) && p->ru0 > 0.0f &&
+        std::isfinite(p->lam0) && p->lam0 > 0.0f)) {
+    *msg = "scalar initial values must be finite and > 0";
+    return RCSCM_EINVAL;
+  }
+  if (p->rule != RCSCM_RULE_NAIVE && p->rule != RCSCM_RULE_ACCEL) {
+    *msg = "unknown rule";
+    return RCSCM_EINVAL;
+  }
+  if (p->schedule < RCSCM_SCHED_AUTO || p->schedule > RCSCM_SCHED_RESIDENT) {
+    *msg = "unknown schedule";
+    return RCSCM_EINVAL;
+  }
+  if (p->lamsum != RCSCM_LAMSUM_F64 && p->lamsum != RCSCM_LAMSUM_KAHAN32) {
+    *msg = "unknown lamsum";
+    return RCSCM_EINVAL;
+  }
+  if (!(p->block == 0 || p->block == 64 || p->block == 128 || p->block == 256 ||
+        p->block == 512 || p->block == 1024)) {
+    *msg = "block must be 0, 64, 128, 256, 512 or 1024";
+    return RCSCM_EINVAL;
+  }
+  if (!(p->chunk == 0 || p->chunk == 256 || p->chunk == 512 || p->chunk == 1024 ||
+        p->chunk == 2048)) {
+    *msg = "chunk must be 0, 256, 512, 1024 or 2048";
+    return RCSCM_EINVAL;
+  }
+  if (p->flags & ~(RCSCM_FLAG_GRAPH | RCSCM_FLAG_CHECKPOINT)) {
+    *msg = "unknown flag bits";
+    return RCSCM_EINVAL;
+  }
+  int maxJ = 0;
+  for (int u = 0; u < U; ++u) maxJ = J[u] > maxJ ? J[u] : maxJ;
+  if ((p->schedule == RCSCM_SCHED_RESIDENT || (p->flags & RCSCM_FLAG_CHECKPOINT)) &&
+      p->rule == RCSCM_RULE_ACCEL) {
+    const int nt = p->block ? p->block : 1024;
+    const int cap = nt == 1024 ? 8 * 1024 : nt * 16;
+    if (maxJ > cap) {
+      *msg = "RESIDENT schedule (or checkpoints) needs J <= 16 * block (8192 for block 1024)";
+      return RCSCM_ESHAPE;
+    }
+  }
+  if ((p->flags & RCSCM_FLAG_CHECKPOINT) && p->rule != RCSCM_RULE_ACCEL) {
+    *msg = "checkpoints (backward) need the ACCEL rule";
+    return RCSCM_EINVAL;
+  }
+  return RCSCM_OK;
+}
+
+static int auto_block(int maxJ) {
+  // smallest workgroup that holds the longest row with at most 8 bins per lane
+  for (int nt : {64, 128, 256, 512, 1024})
+    if (nt * 8 >= maxJ) return nt;
+  return 1024;
+}
+
+static rcscm_status build_tables(rcscm_ctx* c) {
+  const int U = c->U, I = c->I;
+  c->nrows = U * I;
+  long long xoff = 0, boff = 0, aoff = 0, rpoff = 0;
+  c->h_rows.resize(c->nrows);
+  int maxJ = 0;
+  for (int u = 0; u < U; ++u) {
+    const int J = c->J[u], M = c->M[u];
+    maxJ = J > maxJ ? J : maxJ;
+    for (int i = 0; i < I; ++i) {
+      RowInfo& r = c->h_rows[(size_t)u * I + i];
+      r.x_off = xoff + (long long)i * J * M;
+      r.bin_off = boff + (long long)i * J;
+      r.a_off = aoff + (long long)i * M;
+      r.rp_off = rpoff + (long long)i * M * M;
+      r.J = J;
+      r.M = M;
+      r.utt = u;
+      r.freq = i;
+    }
+    xoff += (long long)I * J * M;
+    boff += (long long)I * J;
+    aoff += (long long)I * M;
+    rpoff += (long long)I * M * M;
+  }
+  c->nbins = boff;
+  // chunks (row order); the partial slot of a chunk is its index
+  c->chunk = c->p.chunk ? c->p.chunk : 1024;
+  c->h_chunks.clear();
+  for (int r = 0; r < c->nrows; ++r) {
+    RowInfo& ri = c->h_rows[r];
+    ri.part_off = (int)c->h_chunks.size();
+    for (int s = 0; s < ri.J; s += c->chunk) {
+      ChunkInfo ck;
+      ck.row = r;
+      ck.start = s;
+      ck.len = (ri.J - s) < c->chunk ? (ri.J - s) : c->chunk;
+      ck.part = (int)c->h_chunks.size();
+      c->h_chunks.push_back(ck);
+    }
+    ri.nparts = (int)c->h_chunks.size() - ri.part_off;
+  }
+  c->nchunks = (int)c->h_chunks.size();
+  // the same chunks grouped by microphone count
+  std::vector<ChunkInfo> by_m;
+  by_m.reserve(c->h_chunks.size());
+  for (int m = 2; m <= RCSCM_MAX_M; ++m) {
+    const int start = (int)by_m.size();
+    for (const ChunkInfo& ck : c->h_chunks)
+      if (c->h_rows[ck.row].M == m) by_m.push_back(ck);
+    c->m_range[m] = {start, (int)by_m.size() - start};
+  }
+  // schedule
+  if (c->p.rule == RCSCM_RULE_ACCEL) {
+    const bool fits = maxJ <= kMaxResidentJ;
+    if (c->p.flags & RCSCM_FLAG_CHECKPOINT)
+      c->schedule = RCSCM_SCHED_RESIDENT;
+    else if (c->p.schedule == RCSCM_SCHED_AUTO)
+      c->schedule = fits ? RCSCM_SCHED_RESIDENT : RCSCM_SCHED_STREAM;
+    else
+      c->schedule = c->p.schedule;
+  } else {
+    c->schedule = RCSCM_SCHED_STREAM;
+  }
+  c->res_nt = c->p.block ? c->p.block : auto_block(maxJ);
+  std::vector<int> row_list;
+  c->res_classes.clear();
+  if (c->p.rule == RCSCM_RULE_ACCEL && c->schedule == RCSCM_SCHED_RESIDENT) {
+    std::map<int, std::vector<int>> cls;
+    for (int r = 0; r < c->nrows; ++r) {
+      const int need = (c->h_rows[r].J + c->res_nt - 1) / c->res_nt;
+      int bpl = round_up_bpl(need);
+      while (bpl > 0 && !resident_supported(c->res_nt, bpl)) bpl = round_up_bpl(bpl + 1);
+      if (bpl < 0) return c->fail(RCSCM_ESHAPE, "row too long for the RESIDENT schedule");
+      cls[bpl].push_back(r);
+    }
+    for (auto& kv : cls) {
+      // longest rows first inside the launch order
+      rcscm_ctx::ResClass rc{kv.first, (int)kv.second.size(), (int)row_list.size()};
+      row_list.insert(row_list.end(), kv.second.begin(), kv.second.end());
+      c->res_classes.push_back(rc);
+    }
+  }
+  if (row_list.empty()) row_list.push_back(0);
+  // device copies
+  RCSCM_TRY(c->alloc(&c->d_rows, c->nrows, "rows"));
+  RCSCM_TRY(c->alloc(&c->d_chunks, c->nchunks, "chunks"));
+  RCSCM_TRY(c->alloc(&c->d_chunks_m, c->nchunks, "chunks by M"));
+  RCSCM_TRY(c->alloc(&c->d_row_list, row_list.size(), "row list"));
+  RCSCM_HIP(c, hipMemcpy(c->d_rows, c->h_rows.data(), sizeof(RowInfo) * c->nrows,
+                         hipMemcpyHostToDevice));
+  RCSCM_HIP(c, hipMemcpy(c->d_chunks, c->h_chunks.data(), sizeof(ChunkInfo) * c->nchunks,
+                         hipMemcpyHostToDevice));
+  RCSCM_HIP(c, hipMemcpy(c->d_chunks_m, by_m.data(), sizeof(ChunkInfo) * by_m.size(),
+                         hipMemcpyHostToDevice));
+  RCSCM_HIP(c, hipMemcpy(c->d_row_list, row_list.data(), sizeof(int) * row_list.size(),
+                         hipMemcpyHostToDevice));
+  return RCSCM_OK;
+}
+
+static rcscm_status alloc_workspace(rcscm_ctx* c) {
+  RCSCM_TRY(c->alloc(&c->d_rcd, c->nrows, "row constants (fp64)"));
+  RCSCM_TRY(c->alloc(&c->d_rcf, c->nrows, "row constants"));
+  RCSCM_TRY(c->alloc(&c->d_rsf, c->nrows, "row spatial model"));
+  RCSCM_TRY(c->alloc(&c->d_tsig, c->nbins, "tau/sigma"));
+  RCSCM_TRY(c->alloc(&c->d_nu, c->nbins, "nu"));
+  RCSCM_TRY(c->alloc(&c->d_rh, c->nbins, "r^h"));
+  RCSCM_TRY(c->alloc(&c->d_ru, c->nbins, "r^u"));
+  RCSCM_TRY(c->alloc(&c->d_lam[0], c->nrows, "lambda"));
+  RCSCM_TRY(c->alloc(&c->d_lam[1], c->nrows, "lambda"));
+  RCSCM_TRY(c->alloc(&c->d_part[0], c->nchunks, "partial sums"));
+  RCSCM_TRY(c->alloc(&c->d_part[1], c->nchunks, "partial sums"));
+  RCSCM_TRY(c->alloc(&c->d_status, c->nrows, "status"));
+  RCSCM_TRY(c->alloc(&c->d_objpart, c->nchunks, "objective partials"));
+  if (c->p.rule == RCSCM_RULE_NAIVE) {
+    long long maxMM = 0;
+    for (int u = 0; u < c->U; ++u) maxMM = c->M[u] * c->M[u] > maxMM ? c->M[u] * c->M[u] : maxMM;
+    RCSCM_TRY(c->alloc(&c->d_uhat, (size_t)(maxMM * c->nbins), "packed U^"));
+    RCSCM_TRY(c->alloc(&c->d_rinv, (size_t)c->nrows * MAXM * MAXM, "R^{-1}"));
+  }
+  return RCSCM_OK;
+}
+
+size_t rcscm_workspace_bytes(int U, int I, const int* J, const int* M,
+                             const rcscm_params* params) {
+  rcscm_params p;
+  if (params)
+    p = *params;
+  else
+    rcscm_default_params(&p);
+  std::string msg;
+  if (validate(U, I, J, M, &p, &msg) != RCSCM_OK) return 0;
+  long long bins = 0, chunks = 0, maxMM = 0;
+  const long long chunk = p.chunk ? p.chunk : 1024;
+  for (int u = 0; u < U; ++u) {
+    bins += (long long)I * J[u];
+    chunks += (long long)I * ((J[u] + chunk - 1) / chunk);
+    maxMM = M[u] * M[u] > maxMM ? M[u] * M[u] : maxMM;
+  }
+  const long long rows = (long long)U * I;
+  size_t b = 0;
+  b += rows * (sizeof(RowInfo) + sizeof(RowConstD) + sizeof(RowConstF) + sizeof(RowSpatialF) +
+               2 * sizeof(float) + sizeof(unsigned) + sizeof(int));
+  b += chunks * (2 * sizeof(ChunkInfo) + 2 * sizeof(uint64_t) + sizeof(double));
+  b += bins * (sizeof(float4) + 3 * sizeof(float));
+  if (p.rule == RCSCM_RULE_NAIVE) b += bins * maxMM * sizeof(float) + rows * 64 * sizeof(float2);
+  return b;
+}
+
+static rcscm_status create_impl(rcscm_ctx** out, int U, int I, const int* J, const int* M,
+                                const rcscm_params* params, void* stream) {
+  if (!out) {
+    g_create_error = "out must not be NULL";
+    return RCSCM_EINVAL;
+  }
+  *out = nullptr;
+  rcscm_params p;
+  if (params)
+    p = *params;
+  else
+    rcscm_default_params(&p);
+  std::string msg;
+  rcscm_status s = validate(U, I, J, M, &p, &msg);
+  if (s != RCSCM_OK) {
+    g_create_error = msg;
+    return s;
+  }
+  rcscm_ctx* c = new rcscm_ctx();
+  c->U = U;
+  c->I = I;
+  c->J.assign(J, J + U);
+  c->M.assign(M, M + U);
+  c->p = p;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  s = build_tables(c);
+  if (s == RCSCM_OK) s = alloc_workspace(c);
+  if (s != RCSCM_OK) {
+    g_create_error = c->err;
+    delete c;
+    return s;
+  }
+  *out = c;
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_create(rcscm_ctx** out, int I, int J, int M, const rcscm_params* params,
+                          void* stream) {
+  return create_impl(out, 1, I, &J, &M, params, stream);
+}
+
+rcscm_status rcscm_create_batch(rcscm_ctx** out, int U, int I, const int* J, const int* M,
+                                const rcscm_params* params, void* stream) {
+  return create_impl(out, U, I, J, M, params, stream);
+}
+
+rcscm_status rcscm_init(rcscm_ctx* c, const void* x, const void* a, const void* Rp, const void* b,
+                        const float* rh0, const float* ru0, const float* lam0) {
+  if (!c) return RCSCM_EINVAL;
+  if (!x || !a || !Rp || !b) return c->fail(RCSCM_EINVAL, "x, a, Rp and b must not be NULL");
+  hipStream_t s = c->stream;
+  RCSCM_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(unsigned) * c->nrows, s));
+  c->lam_cur = 0;
+  launch_setup(s, c->nrows, c->d_rows, static_cast<const double2*>(a),
+               static_cast<const double2*>(Rp), static_cast<const double2*>(b), c->d_rcd,
+               c->d_rcf, c->d_rsf, c->d_status);
+  RCSCM_HIP(c, hipGetLastError());
+  for (int m = 2; m <= RCSCM_MAX_M; ++m) {
+    const auto rg = c->m_range[m];
+    if (rg.second == 0) continue;
+    launch_precompute(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rcd,
+                      static_cast<const float2*>(x), c->d_tsig, c->d_nu, c->d_status);
+    RCSCM_HIP(c, hipGetLastError());
+  }
+  launch_fill_state(s, c->nrows, c->d_rows, rh0, ru0, lam0, c->p.rh0, c->p.ru0, c->p.lam0,
+                    c->d_rh, c->d_ru, c->d_lam[c->lam_cur], c->d_status);
+  RCSCM_HIP(c, hipGetLastError());
+  c->x_borrowed = static_cast<const float2*>(x);
+  c->inited = true;
+  c->ck_K = -1;
+  return RCSCM_OK;
+}
+
+static rcscm_status enqueue_stream_loop(rcscm_ctx* c, int K) {
+  hipStream_t s = c->stream;
+  const float alpha = (float)c->p.alpha, beta = (float)c->p.beta;
+  int cur = c->lam_cur;
+  for (int k = 1; k <= K + 1; ++k) {
+    const bool finish = k >= 2;
+    const bool start = k <= K;
+    const float* lam_prev = c->d_lam[cur];
+    float* lam_new = c->d_lam[cur ^ 1];
+    const uint64_t* part_in = finish ? c->d_part[(k - 2) & 1] : nullptr;
+    uint64_t* part_out = start ? c->d_part[(k - 1) & 1] : nullptr;
+    launch_accel_stream(s, c->p.lamsum, finish, start, c->nchunks, c->d_chunks, c->d_rows,
+                        c->d_rcf, c->d_tsig, c->d_nu, c->d_rh, c->d_ru, lam_prev, lam_new, part_in,
+                        part_out, alpha, beta, c->chunk, c->d_status);
+    RCSCM_HIP(c, hipGetLastError());
+    if (finish) cur ^= 1;
+  }
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
+  if (!c) return RCSCM_EINVAL;
+  if (K < 0) return c->fail(RCSCM_ESHAPE, "K must be >= 0");
+  if (!c->inited) return c->fail(RCSCM_ESTATE, "iterate before init");
+  if (K == 0) return RCSCM_OK;
+  hipStream_t s = c->stream;
+  const float alpha = (float)c->p.alpha, beta = (float)c->p.beta;
+  if (c->p.rule == RCSCM_RULE_NAIVE) {
+    for (int k = 0; k < K; ++k) {
+      for (int m = 2; m <= RCSCM_MAX_M; ++m) {
+        const auto rg = c->m_range[m];
+        if (rg.second == 0) continue;
+        launch_naive_a(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rsf,
+                       c->x_borrowed, c->d_rh, c->d_ru, c->d_lam[c->lam_cur], c->d_uhat, c->nbins,
+                       c->d_part[0], alpha, beta, c->d_status);
+        RCSCM_HIP(c, hipGetLastError());
+      }
+      launch_naive_rinv(s, c->nrows, c->d_rows, c->d_rcd, c->d_part[0], c->d_lam[c->lam_cur],
+                        c->d_rinv, c->d_status);
+      RCSCM_HIP(c, hipGetLastError());
+      for (int m = 2; m <= RCSCM_MAX_M; ++m) {
+        const auto rg = c->m_range[m];
+        if (rg.second == 0) continue;
+        launch_naive_b(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rinv, c->d_ru,
+                       c->d_uhat, c->nbins, c->d_status);
+        RCSCM_HIP(c, hipGetLastError());
+      }
+    }
+    return RCSCM_OK;
+  }
+  if (c->schedule == RCSCM_SCHED_RESIDENT) {
+    float *ck_rh = nullptr, *ck_ru = nullptr, *ck_lam = nullptr;
+    if (c->p.flags & RCSCM_FLAG_CHECKPOINT) {
+      if (K > c->ck_capacity) {
+        RCSCM_TRY(c->alloc(&c->d_ck_rh, (size_t)K * c->nbins, "checkpoints r^h"));
+        RCSCM_TRY(c->alloc(&c->d_ck_ru, (size_t)K * c->nbins, "checkpoints r^u"));
+        RCSCM_TRY(c->alloc(&c->d_ck_lam, (size_t)K * c->nrows, "checkpoints lambda"));
+        c->ck_capacity = K;
+      }
+      ck_rh = c->d_ck_rh;
+      ck_ru = c->d_ck_ru;
+      ck_lam = c->d_ck_lam;
+      c->ck_K = K;
+    }
+    for (const auto& cl : c->res_classes) {
+      launch_accel_resident(s, c->res_nt, cl.bpl, c->p.lamsum, cl.count, c->d_row_list + cl.offset,
+                            c->d_rows, c->d_rcf, c->d_tsig, c->d_nu, c->d_rh, c->d_ru,
+                            c->d_lam[c->lam_cur], alpha, beta, K, ck_rh, ck_ru, ck_lam, c->nbins,
+                            c->nrows, c->d_status);
+      RCSCM_HIP(c, hipGetLastError());
+    }
+    return RCSCM_OK;
+  }
+  // STREAM
+  if (c->p.flags & RCSCM_FLAG_GRAPH) {
+    const std::pair<int, int> key{K, c->lam_cur};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      hipStream_t cap = nullptr;
+      RCSCM_HIP(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      hipStream_t saved = c->stream;
+      c->stream = cap;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      rcscm_status st = RCSCM_OK;
+      if (e == hipSuccess) st = enqueue_stream_loop(c, K);
+      hipError_t e2 = hipStreamEndCapture(cap, &g);
+      c->stream = saved;
+      (void)hipStreamDestroy(cap);
+      if (e != hipSuccess || e2 != hipSuccess || st != RCSCM_OK)
+        return c->fail(RCSCM_EDEVICE, "hipGraph capture of the iteration loop failed");
+      hipGraphExec_t ex = nullptr;
+      RCSCM_HIP(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      c->graph_defs.push_back(g);
+      it = c->graphs.emplace(key, ex).first;
+    }
+    RCSCM_HIP(c, hipGraphLaunch(it->second, s));
+    c->lam_cur ^= (K & 1);
+    return RCSCM_OK;
+  }
+  RCSCM_TRY(enqueue_stream_loop(c, K));
+  c->lam_cur ^= (K & 1);
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_extract(rcscm_ctx* c, float* rh, float* ru, float* lam, void* s_hat) {
+  if (!c) return RCSCM_EINVAL;
+  if (!c->inited) return c->fail(RCSCM_ESTATE, "extract before init");
+  if (!rh && !ru && !lam && !s_hat) return RCSCM_OK;
+  launch_extract(c->stream, c->nchunks, c->d_chunks, c->d_rows, c->d_rcf, c->d_tsig, c->d_rh,
+                 c->d_ru, c->d_lam[c->lam_cur], rh, ru, lam, static_cast<float2*>(s_hat),
+                 c->d_status);
+  RCSCM_HIP(c, hipGetLastError());
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_set_state(rcscm_ctx* c, const float* rh, const float* ru, const float* lam) {
+  if (!c) return RCSCM_EINVAL;
+  if (!c->inited) return c->fail(RCSCM_ESTATE, "set_state before init");
+  if (!rh || !ru || !lam) return c->fail(RCSCM_EINVAL, "state arrays must not be NULL");
+  hipStream_t s = c->stream;
+  RCSCM_HIP(c, hipMemcpyAsync(c->d_rh, rh, sizeof(float) * c->nbins, hipMemcpyDeviceToDevice, s));
+  RCSCM_HIP(c, hipMemcpyAsync(c->d_ru, ru, sizeof(float) * c->nbins, hipMemcpyDeviceToDevice, s));
+  RCSCM_HIP(c, hipMemcpyAsync(c->d_lam[c->lam_cur], lam, sizeof(float) * c->nrows,
+                              hipMemcpyDeviceToDevice, s));
+  c->ck_K = -1;
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_sync(rcscm_ctx* c) {
+  if (!c) return RCSCM_EINVAL;
+  RCSCM_HIP(c, hipStreamSynchronize(c->stream));
+  if (!c->inited) return RCSCM_OK;
+  std::vector<unsigned> st(c->nrows);
+  RCSCM_HIP(c, hipMemcpy(st.data(), c->d_status, sizeof(unsigned) * c->nrows,
+                         hipMemcpyDeviceToHost));
+  const unsigned order[] = {ST_NONFINITE_IN, ST_NOT_NULL, ST_NOT_PSD, ST_NONFINITE_STATE,
+                            ST_LAM_NONPOS};
+  for (unsigned bit : order) {
+    for (int r = 0; r < c->nrows; ++r) {
+      if (st[r] & bit) {
+        const RowInfo& ri = c->h_rows[r];
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "row %d (utterance %d, frequency %d): %s", r, ri.utt,
+                      ri.freq,
+                      bit == ST_NONFINITE_IN     ? "non-finite input"
+                      : bit == ST_NOT_NULL       ? "b is not a null vector of R'"
+                      : bit == ST_NOT_PSD        ? "R' + b b^H is not positive definite"
+                      : bit == ST_NONFINITE_STATE ? "non-finite or non-positive state"
+                                                 : "lambda is not positive");
+        c->err = buf;
+        switch (bit) {
+          case ST_NONFINITE_IN: return RCSCM_ENONFINITE;
+          case ST_NOT_NULL: return RCSCM_ENOTNULL;
+          case ST_NOT_PSD: return RCSCM_ENOTPSD;
+          default: return RCSCM_ENONFINITE;
+        }
+      }
+    }
+  }
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_objective(rcscm_ctx* c, double* nlp) {
+  if (!c || !nlp) return RCSCM_EINVAL;
+  if (!c->inited) return c->fail(RCSCM_ESTATE, "objective before init");
+  launch_objective(c->stream, c->nchunks, c->d_chunks, c->d_rows, c->d_rcf, c->d_rcd, c->d_tsig,
+                   c->d_nu, c->d_rh, c->d_ru, c->d_lam[c->lam_cur], c->p.alpha, c->p.beta,
+                   c->d_objpart);
+  RCSCM_HIP(c, hipGetLastError());
+  RCSCM_HIP(c, hipStreamSynchronize(c->stream));
+  std::vector<double> part(c->nchunks);
+  RCSCM_HIP(c, hipMemcpy(part.data(), c->d_objpart, sizeof(double) * c->nchunks,
+                         hipMemcpyDeviceToHost));
+  double sum = 0.0;
+  for (double v : part) sum += v;
+  *nlp = sum;
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_backward(rcscm_ctx* c, const void* x, const void* grad_s_hat, void* grad_x,
+                            float* grad_rh0, float* grad_lam0) {
+  if (!c) return RCSCM_EINVAL;
+  if (!(c->p.flags & RCSCM_FLAG_CHECKPOINT) || c->ck_K < 0)
+    return c->fail(RCSCM_ESTATE, "backward needs a context with checkpoints that was iterated");
+  if (!x || !grad_s_hat) return c->fail(RCSCM_EINVAL, "x and grad_s_hat must not be NULL");
+  return c->fail(RCSCM_ESTATE, "backward is not built yet");
+  for (const auto& cl : c->res_classes) {
+    launch_backward(c->stream, c->res_nt, cl.bpl, cl.count, c->d_row_list + cl.offset, c->d_rows,
+                    c->d_rcf, c->d_rcd, static_cast<const float2*>(x), c->d_tsig, c->d_nu,
+                    c->d_ck_rh, c->d_ck_ru, c->d_ck_lam, c->nbins, c->nrows, c->ck_K,
+                    (float)c->p.alpha, (float)c->p.beta, static_cast<const float2*>(grad_s_hat),
+                    static_cast<float2*>(grad_x), grad_rh0, grad_lam0, c->d_status);
+    RCSCM_HIP(c, hipGetLastError());
+  }
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_get_schedule(const rcscm_ctx* c, int* schedule, int* block, int* chunk) {
+  if (!c) return RCSCM_EINVAL;
+  if (schedule) *schedule = c->schedule;
+  if (block) *block = c->res_nt;
+  if (chunk) *chunk = c->chunk;
+  return RCSCM_OK;
+}
+
+void rcscm_destroy(rcscm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
+  delete c;
+}
+
+const char* rcscm_last_error(const rcscm_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,365 @@
+// Naive EM update (Sec. II-B-2, eqs. (13)-(20)) on gfx950: the comparator.
+//
+// One iteration is three launches:
+//   naive_a   (per chunk of bins)  E-step with one M x M factorisation per bin
+//             and the r^h update:
+//               R~    = R' + lambda~ b b^H                          eq. (13)
+//               Sigma = r~h a a^H + r~u R~ = L L^H  (float Cholesky) eq. (14)
+//               p = L^{-1} a, w = L^{-1} x, Y = L^{-1} R~
+//               h^    = r~h - r~h^2 |p|^2 + r~h^2 |w^H p|^2          eq. (15)
+//               U^    = r~u R~ - r~u^2 Y^H Y + r~u^2 (Y^H w)(Y^H w)^H eq. (16)
+//               r^h   = (h^ + beta) / (alpha + 2)                    eq. (17)
+//             U^ is stored packed (M real diagonal entries, then the
+//             upper triangle) and the chunk's sum of b^H U^ b / r~u is
+//             written as a partial sum for eq. (18).
+//   naive_rinv (per row)  lambda = mean of the partial sums (eq. (18)),
+//             R = R' + lambda b b^H (eq. (19)) and R^{-1} by an FP64
+//             Cholesky factorisation.
+//   naive_b   (per chunk)  r^u = tr(R^{-1} U^) / M                      eq. (20)
+// No step uses the pseudoinverse of R' or the Sherman-Morrison identity.
+#include "accel_common.h"
+
+namespace rcscm {
+
+namespace {
+
+constexpr int kNT = 256;
+
+struct cf {
+  float x, y;
+};
+__device__ __forceinline__ cf cmk(float x, float y) { return cf{x, y}; }
+__device__ __forceinline__ cf operator+(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cf operator-(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cf cmul(cf a, cf b) {
+  return cf{fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x)};
+}
+__device__ __forceinline__ cf cmulc(cf a, cf b) {  // conj(a) b
+  return cf{fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -a.y * b.x)};
+}
+__device__ __forceinline__ cf cscale(cf a, float s) { return cf{a.x * s, a.y * s}; }
+__device__ __forceinline__ float cabs2(cf a) { return fmaf(a.x, a.x, a.y * a.y); }
+
+template <int M>
+__global__ __launch_bounds__(kNT) void naive_a_kernel(
+    const ChunkInfo* __restrict__ chunks, const RowInfo* __restrict__ rows,
+    const RowSpatialF* __restrict__ rsf, const float2* __restrict__ x, float* __restrict__ rh,
+    const float* __restrict__ ru, const float* __restrict__ lam, float* __restrict__ uhat,
+    long long nbins, uint64_t* __restrict__ part, float inv_a2, float beta_a2,
+    unsigned* __restrict__ status) {
+  const ChunkInfo ck = chunks[blockIdx.x];
+  const RowInfo ri = rows[ck.row];
+  const int t = threadIdx.x;
+  __shared__ cf sRt[M][M];  // R~ = R' + lambda~ b b^H
+  __shared__ cf sa[M], sb[M];
+  __shared__ uint64_t red[kNT / 64];
+  const RowSpatialF* S = rsf + ck.row;
+  const float lam_t = lam[ck.row];
+  if (t < M * M) {
+    const int i = t / M, j = t % M;
+    const float2 r = S->Rp[i * MAXM + j];
+    const float2 bi = S->b[i], bj = S->b[j];
+    const cf bb = cmul(cmk(bi.x, bi.y), cmk(bj.x, -bj.y));
+    sRt[i][j] = cmk(fmaf(lam_t, bb.x, r.x), fmaf(lam_t, bb.y, r.y));
+  }
+  if (t < M) {
+    sa[t] = cmk(S->a[t].x, S->a[t].y);
+    sb[t] = cmk(S->b[t].x, S->b[t].y);
+  }
+  __syncthreads();
+
+  LamAcc<0> acc;
+  bool bad = false;
+  for (int jj = t; jj < ck.len; jj += kNT) {
+    const long long bin = ri.bin_off + ck.start + jj;
+    const float2* xp = x + ri.x_off + (long long)(ck.start + jj) * M;
+    cf xv[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) xv[m] = cmk(xp[m].x, xp[m].y);
+    const float h = rh[bin], u = ru[bin];
+
+    // lower triangle of Sigma, then Cholesky in place (real diagonal)
+    cf L[M][M];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        const cf aa = cmulc(sa[j], sa[i]);  // a_i conj(a_j)
+        L[i][j] = cmk(fmaf(h, aa.x, u * sRt[i][j].x), fmaf(h, aa.y, u * sRt[i][j].y));
+      }
+    float dinv[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      float d = L[j][j].x;
+#pragma unroll
+      for (int k = 0; k < j; ++k) d -= cabs2(L[j][k]);
+      bad = bad || !(d > 0.0f);
+      const float is = rsqrtf(fmaxf(d, 1e-37f));
+      L[j][j] = cmk(d * is, 0.0f);
+      dinv[j] = is;
+#pragma unroll
+      for (int i = j + 1; i < M; ++i) {
+        cf s = L[i][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s = s - cmul(L[i][k], cmk(L[j][k].x, -L[j][k].y));
+        L[i][j] = cscale(s, is);
+      }
+    }
+    // forward substitutions with L
+    auto fwd = [&](const cf* v, cf* y) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        cf s = v[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s = s - cmul(L[i][k], y[k]);
+        y[i] = cscale(s, dinv[i]);
+      }
+    };
+    cf p[M], w[M];
+    fwd(sa, p);
+    fwd(xv, w);
+    cf Y[M][M];  // Y[:, n] = L^{-1} R~[:, n]
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      cf col[M], yc[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) col[i] = sRt[i][n];
+      fwd(col, yc);
+#pragma unroll
+      for (int i = 0; i < M; ++i) Y[i][n] = yc[i];
+    }
+    float pp = 0.0f;
+    cf wp = cmk(0.0f, 0.0f);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      pp += cabs2(p[i]);
+      wp = wp + cmulc(w[i], p[i]);
+    }
+    const float hh = h - h * h * pp + h * h * cabs2(wp);
+    rh[bin] = fmaf(hh, inv_a2, beta_a2);
+
+    cf v[M];  // Y^H w = R~ Sigma^{-1} x
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      cf s = cmk(0.0f, 0.0f);
+#pragma unroll
+      for (int k = 0; k < M; ++k) s = s + cmulc(Y[k][m], w[k]);
+      v[m] = s;
+    }
+    const float u2 = u * u;
+    // packed U^: diagonal (real) first, then (m < n) pairs
+    float bUb = 0.0f;
+    int e = M;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+#pragma unroll
+      for (int n = m; n < M; ++n) {
+        cf yy = cmk(0.0f, 0.0f);
+#pragma unroll
+        for (int k = 0; k < M; ++k) yy = yy + cmulc(Y[k][m], Y[k][n]);
+        const cf vv = cmul(v[m], cmk(v[n].x, -v[n].y));
+        const cf U = cmk(fmaf(u, sRt[m][n].x, u2 * (vv.x - yy.x)),
+                         fmaf(u, sRt[m][n].y, u2 * (vv.y - yy.y)));
+        if (m == n) {
+          uhat[(long long)m * nbins + bin] = U.x;
+          bUb = fmaf(cabs2(sb[m]), U.x, bUb);
+        } else {
+          uhat[(long long)e * nbins + bin] = U.x;
+          uhat[(long long)(e + 1) * nbins + bin] = U.y;
+          e += 2;
+          // 2 Re(conj(b_m) U_mn b_n)
+          const cf t1 = cmul(cmulc(sb[m], U), sb[n]);
+          bUb = fmaf(2.0f, t1.x, bUb);
+        }
+      }
+    }
+    acc.add(bUb / u);
+  }
+  acc = wave_allreduce<0>(acc);
+  if ((t & 63) == 0) red[t >> 6] = acc.pack();
+  __syncthreads();
+  if (t == 0) {
+    LamAcc<0> tot;
+#pragma unroll
+    for (int w2 = 0; w2 < kNT / 64; ++w2) tot.combine(LamAcc<0>::unpack(red[w2]));
+    part[ck.part] = tot.pack();
+  }
+  if (bad) atomicOr(status + ck.row, ST_NONFINITE_STATE);
+}
+
+__device__ inline double2 dmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// lambda from the partial sums, then R^{-1} = (R' + lambda b b^H)^{-1} in FP64.
+__global__ __launch_bounds__(64) void naive_rinv_kernel(const RowInfo* __restrict__ rows,
+                                                        const RowConstD* __restrict__ rcd,
+                                                        const uint64_t* __restrict__ part,
+                                                        float* __restrict__ lam,
+                                                        float2* __restrict__ rinv,
+                                                        unsigned* __restrict__ status) {
+  const int r = blockIdx.x;
+  const int t = threadIdx.x;
+  const RowInfo ri = rows[r];
+  const int M = ri.M;
+  const RowConstD* D = rcd + r;
+  __shared__ double2 sA[MAXM][MAXM], sL[MAXM][MAXM], sLi[MAXM][MAXM];
+  __shared__ double sinv;
+  const float l = wave_sum_packed<0>(part + ri.part_off, ri.nparts).mean(1.0 / (double)ri.J);
+  if (t == 0) {
+    lam[r] = l;
+    if (!(l > 0.0f) || !isfinite(l)) atomicOr(status + r, ST_LAM_NONPOS);
+  }
+  const double ld = (double)l;
+  if (t < M * M) {
+    const int i = t / M, j = t % M;
+    const double2 bi = D->b[i], bj = D->b[j];
+    const double2 bb = dmul(bi, make_double2(bj.x, -bj.y));
+    const double2 rp = D->Rp[i * MAXM + j];
+    sA[i][j] = make_double2(rp.x + ld * bb.x, rp.y + ld * bb.y);
+    sL[i][j] = make_double2(0.0, 0.0);
+    sLi[i][j] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < M; ++k) {
+    if (t == 0) {
+      const double d = fmax(sA[k][k].x, 1e-300);
+      const double lk = sqrt(d);
+      sL[k][k] = make_double2(lk, 0.0);
+      sinv = 1.0 / lk;
+    }
+    __syncthreads();
+    if (t > k && t < M) sL[t][k] = make_double2(sA[t][k].x * sinv, sA[t][k].y * sinv);
+    __syncthreads();
+    if (t < M * M) {
+      const int i = t / M, j = t % M;
+      if (j > k && i >= j) {
+        const double2 p = dmul(sL[i][k], make_double2(sL[j][k].x, -sL[j][k].y));
+        sA[i][j].x -= p.x;
+        sA[i][j].y -= p.y;
+      }
+    }
+    __syncthreads();
+  }
+  if (t < M) {  // column t of L^{-1}
+    const int j = t;
+    for (int i = j; i < M; ++i) {
+      double2 s = make_double2(i == j ? 1.0 : 0.0, 0.0);
+      for (int k = j; k < i; ++k) {
+        const double2 p = dmul(sL[i][k], sLi[k][j]);
+        s.x -= p.x;
+        s.y -= p.y;
+      }
+      const double inv = 1.0 / sL[i][i].x;
+      sLi[i][j] = make_double2(s.x * inv, s.y * inv);
+    }
+  }
+  __syncthreads();
+  if (t < M * M) {  // R^{-1} = L^{-H} L^{-1}: (i, j) = sum_k conj(Li[k][i]) Li[k][j]
+    const int i = t / M, j = t % M;
+    double2 s = make_double2(0.0, 0.0);
+    for (int k = 0; k < M; ++k) {
+      const double2 p = dmul(make_double2(sLi[k][i].x, -sLi[k][i].y), sLi[k][j]);
+      s.x += p.x;
+      s.y += p.y;
+    }
+    rinv[(long long)r * (MAXM * MAXM) + i * MAXM + j] = make_float2((float)s.x, (float)s.y);
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(kNT) void naive_b_kernel(const ChunkInfo* __restrict__ chunks,
+                                                      const RowInfo* __restrict__ rows,
+                                                      const float2* __restrict__ rinv,
+                                                      float* __restrict__ ru,
+                                                      const float* __restrict__ uhat,
+                                                      long long nbins,
+                                                      unsigned* __restrict__ status) {
+  const ChunkInfo ck = chunks[blockIdx.x];
+  const RowInfo ri = rows[ck.row];
+  const int t = threadIdx.x;
+  __shared__ float2 sR[M * M];
+  if (t < M * M) sR[t] = rinv[(long long)ck.row * (MAXM * MAXM) + (t / M) * MAXM + (t % M)];
+  __syncthreads();
+  bool bad = false;
+  for (int jj = t; jj < ck.len; jj += kNT) {
+    const long long bin = ri.bin_off + ck.start + jj;
+    float tr = 0.0f;
+#pragma unroll
+    for (int m = 0; m < M; ++m) tr = fmaf(sR[m * M + m].x, uhat[(long long)m * nbins + bin], tr);
+    int e = M;
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int n = m + 1; n < M; ++n) {
+        const float ur = uhat[(long long)e * nbins + bin];
+        const float ui = uhat[(long long)(e + 1) * nbins + bin];
+        e += 2;
+        // 2 Re(Rinv[n][m] U[m][n])
+        const float2 r = sR[n * M + m];
+        tr = fmaf(2.0f, fmaf(r.x, ur, -r.y * ui), tr);
+      }
+    const float v = tr * (1.0f / (float)M);
+    ru[bin] = v;
+    bad = bad || !isfinite(v);
+  }
+  if (bad) atomicOr(status + ck.row, ST_NONFINITE_STATE);
+}
+
+}  // namespace
+
+void launch_naive_a(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
+                    const RowInfo* rows, const RowSpatialF* rsf, const float2* x, float* rh,
+                    const float* ru, const float* lam, float* uhat, long long nbins,
+                    uint64_t* part, float alpha, float beta, unsigned* status) {
+  if (nchunks <= 0) return;
+  const float inv_a2 = (float)(1.0 / ((double)alpha + 2.0));
+  const float beta_a2 = (float)((double)beta / ((double)alpha + 2.0));
+#define RCSCM_NA(MM)                                                                          \
+  case MM:                                                                                    \
+    hipLaunchKernelGGL(naive_a_kernel<MM>, dim3(nchunks), dim3(kNT), 0, s, chunks, rows, rsf, \
+                       x, rh, ru, lam, uhat, nbins, part, inv_a2, beta_a2, status);            \
+    break;
+  switch (M) {
+    RCSCM_NA(2)
+    RCSCM_NA(3)
+    RCSCM_NA(4)
+    RCSCM_NA(5)
+    RCSCM_NA(6)
+    RCSCM_NA(7)
+    RCSCM_NA(8)
+    default: break;
+  }
+#undef RCSCM_NA
+}
+
+void launch_naive_rinv(hipStream_t s, int nrows, const RowInfo* rows, const RowConstD* rcd,
+                       const uint64_t* part, float* lam, float2* rinv, unsigned* status) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(naive_rinv_kernel, dim3(nrows), dim3(64), 0, s, rows, rcd, part, lam, rinv,
+                     status);
+}
+
+void launch_naive_b(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
+                    const RowInfo* rows, const float2* rinv, float* ru, const float* uhat,
+                    long long nbins, unsigned* status) {
+  if (nchunks <= 0) return;
+#define RCSCM_NB(MM)                                                                          \
+  case MM:                                                                                    \
+    hipLaunchKernelGGL(naive_b_kernel<MM>, dim3(nchunks), dim3(kNT), 0, s, chunks, rows, rinv, \
+                       ru, uhat, nbins, status);                                              \
+    break;
+  switch (M) {
+    RCSCM_NB(2)
+    RCSCM_NB(3)
+    RCSCM_NB(4)
+    RCSCM_NB(5)
+    RCSCM_NB(6)
+    RCSCM_NB(7)
+    RCSCM_NB(8)
+    default: break;
+  }
+#undef RCSCM_NB
+}
+
+}  // namespace rcscm

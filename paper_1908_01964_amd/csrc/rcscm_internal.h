@@ -1,0 +1,130 @@
+// Internal types shared by the host code and the HIP kernels of librcscm.
+// Not part of the public ABI (include/rcscm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcscm {
+
+constexpr int MAXM = 8;
+
+// One (utterance, frequency) row: J frames of one frequency bin.
+struct RowInfo {
+  long long x_off;    // complex64 offset of x[row][j=0][m=0] in the packed x
+  long long bin_off;  // offset of frame 0 in every per-bin array
+  long long a_off;    // complex128 offset of a[row][0] (and b[row][0])
+  long long rp_off;   // complex128 offset of R'[row][0][0]
+  int J, M, utt, freq;
+  int part_off;       // first partial-sum slot of this row (STREAM / NAIVE)
+  int nparts;         // number of chunks of this row
+};
+
+// Work unit of the chunked kernels: bins [start, start+len) of one row.
+struct ChunkInfo {
+  int row, start, len, part;  // part = partial-sum slot written by this chunk
+};
+
+// Float per-row constants read by the per-bin iteration.
+struct RowConstF {
+  float t_aa;      // tau^(aa) = a^H (R')^+ a
+  float sab_re;    // sigma^(ab) = a^H b
+  float sab_im;
+  float sab2;      // |sigma^(ab)|^2
+  float inv_t_aa;  // 1 / tau^(aa), or 0 when tau^(aa) == 0
+  float invM;      // 1 / M
+  float invJ;      // 1 / J
+  float pad;
+};
+
+// FP64 per-row setup results (precompute, objective, adjoint).
+struct RowConstD {
+  double2 G[MAXM * MAXM];  // F^H with F F^H = (R')^+, row-major (z = G x)
+  double2 c[MAXM];         // (R')^+ a
+  double2 g[MAXM];         // F^H a  (|g|^2 = tau^(aa))
+  double2 b[MAXM];         // unit null vector of R'
+  double2 a[MAXM];         // steering vector
+  double2 Rp[MAXM * MAXM]; // projected, Hermitised R' (R' b = 0), row-major
+  double2 s_ab;            // a^H b
+  double t_aa;             // a^H (R')^+ a
+  double logpdet;          // log of the pseudo-determinant of R'
+};
+
+// Float spatial model for the naive rule: a, b and the projected R'.
+struct RowSpatialF {
+  float2 a[MAXM];
+  float2 b[MAXM];
+  float2 Rp[MAXM * MAXM];  // row-major, Hermitian, R' b = 0
+};
+
+// Per-row status bits written by kernels.
+enum : unsigned {
+  ST_B_NOT_UNIT = 1u,       // warning: ||b|| differed from 1 by > 1e-6 (normalised)
+  ST_NOT_NULL = 2u,         // ||R' b|| > 1e-6 ||R'||_F, or b == 0
+  ST_NOT_PSD = 4u,          // R' + s b b^H has a non-positive pivot
+  ST_NONFINITE_IN = 8u,     // non-finite x, a, R' or b
+  ST_NONFINITE_STATE = 16u, // non-finite r^h / r^u produced
+  ST_LAM_NONPOS = 32u,      // lambda <= 0 or non-finite
+};
+
+// Kernel launchers (defined in the .hip files).
+void launch_setup(hipStream_t s, int nrows, const RowInfo* rows, const double2* a,
+                  const double2* Rp, const double2* b, RowConstD* rcd, RowConstF* rcf,
+                  RowSpatialF* rsf, unsigned* status);
+
+void launch_precompute(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
+                       const RowInfo* rows, const RowConstD* rcd, const float2* x,
+                       float4* tsig, float* nu, unsigned* status);
+
+void launch_fill_state(hipStream_t s, int nrows, const RowInfo* rows, const float* rh0,
+                       const float* ru0, const float* lam0, float rh_c, float ru_c, float lam_c,
+                       float* rh, float* ru, float* lam, unsigned* status);
+
+// RESIDENT schedule: rows in row_list (all with J <= nt * bpl).
+bool resident_supported(int nt, int bpl);
+void launch_accel_resident(hipStream_t s, int nt, int bpl, int lamsum, int nrows,
+                           const int* row_list, const RowInfo* rows, const RowConstF* rcf,
+                           const float4* tsig, const float* nu, float* rh, float* ru, float* lam,
+                           float alpha, float beta, int K, float* ckpt_rh, float* ckpt_ru,
+                           float* ckpt_lam, long long ckpt_stride_bins, int ckpt_stride_rows,
+                           unsigned* status);
+
+// STREAM schedule: one launch of stage (finish iteration k-1, start iteration k).
+void launch_accel_stream(hipStream_t s, int lamsum, bool finish_prev, bool start_next,
+                         int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
+                         const RowConstF* rcf, const float4* tsig, const float* nu, float* rh,
+                         float* ru, const float* lam_prev, float* lam_new,
+                         const uint64_t* part_in, uint64_t* part_out, float alpha, float beta,
+                         int chunk_threads, unsigned* status);
+
+void launch_extract(hipStream_t s, int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
+                    const RowConstF* rcf, const float4* tsig, const float* rh_in,
+                    const float* ru_in, const float* lam_in, float* rh_out, float* ru_out,
+                    float* lam_out, float2* s_hat, unsigned* status);
+
+void launch_objective(hipStream_t s, int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
+                      const RowConstF* rcf, const RowConstD* rcd, const float4* tsig,
+                      const float* nu, const float* rh, const float* ru, const float* lam,
+                      double alpha, double beta, double* partial);
+
+// NAIVE rule, one iteration = phase A launch + phase B launch per M class.
+void launch_naive_a(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
+                    const RowInfo* rows, const RowSpatialF* rsf, const float2* x, float* rh,
+                    const float* ru, const float* lam, float* uhat, long long nbins,
+                    uint64_t* part, float alpha, float beta, unsigned* status);
+void launch_naive_rinv(hipStream_t s, int nrows, const RowInfo* rows, const RowConstD* rcd,
+                       const uint64_t* part, float* lam, float2* rinv, unsigned* status);
+void launch_naive_b(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
+                    const RowInfo* rows, const float2* rinv, float* ru, const float* uhat,
+                    long long nbins, unsigned* status);
+
+// Adjoint of the RESIDENT/STREAM accelerated forward (checkpointed).
+void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_list,
+                     const RowInfo* rows, const RowConstF* rcf, const RowConstD* rcd,
+                     const float2* x, const float4* tsig, const float* nu,
+                     const float* ckpt_rh, const float* ckpt_ru, const float* ckpt_lam,
+                     long long ckpt_stride_bins, int ckpt_stride_rows, int K, float alpha,
+                     float beta, const float2* grad_s, float2* grad_x, float* grad_rh0,
+                     float* grad_lam0, unsigned* status);
+
+}  // namespace rcscm

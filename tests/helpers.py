@@ -1,0 +1,82 @@
+"""Shared helpers of the GPU parity tests: run the HIP path and the FP64 oracle on the same input."""
+import numpy as np
+
+from oracle import accel as o_accel
+from oracle import extract as o_extract
+from oracle import naive as o_naive
+from synth import ALPHA, BETA
+
+TOL = 1e-4  # normwise relative error after K iterations (FP32 kernel vs FP64 oracle)
+
+
+def nrel(est, ref):
+    est = np.asarray(est).ravel()
+    ref = np.asarray(ref).ravel()
+    return float(np.linalg.norm(est - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def gpu_run(problems, K, init_arrays=None, **params):
+    """Runs init + iterate(K) + extract on the GPU; returns per-utterance numpy dicts."""
+    import torch
+
+    from paper_1908_01964_amd import Context, to_device
+    probs = problems if isinstance(problems, (list, tuple)) else [problems]
+    I = probs[0].x.shape[0]
+    Js = [p.x.shape[1] for p in probs]
+    Ms = [p.x.shape[2] for p in probs]
+    x, a, Rp, b = to_device(probs)
+    ctx = Context(I, Js, Ms, **params)
+    kw = {}
+    if init_arrays is not None:
+        kw = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32).ravel()).cuda()
+              for k, v in init_arrays.items()}
+    ctx.init(x, a, Rp, b, **kw)
+    ctx.iterate(K)
+    out = ctx.extract()
+    ctx.sync()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    ctx.close()
+    return split(res, I, Js)
+
+
+def split(res, I, Js):
+    outs = []
+    bo, ro = 0, 0
+    for J in Js:
+        d = {}
+        for k in ("rh", "ru", "s_hat"):
+            if k in res:
+                d[k] = res[k][bo:bo + I * J].reshape(I, J)
+        d["lam"] = res["lam"][ro:ro + I]
+        outs.append(d)
+        bo += I * J
+        ro += I
+    return outs
+
+
+def oracle_accel(p, K, rh0=None, ru0=None, lam0=None, alpha=ALPHA, beta=BETA):
+    st = o_accel.init_state(p.I, p.J)
+    rh0 = st[0] if rh0 is None else rh0
+    ru0 = st[1] if ru0 is None else ru0
+    lam0 = st[2] if lam0 is None else lam0
+    rh, ru, lam = o_accel.run(p.x, p.a, p.Rp, p.b, rh0, ru0, lam0, K, alpha, beta)
+    sh = o_extract.s_hat(p.x, p.a, p.Rp, p.b, rh, ru, lam)
+    return dict(rh=rh, ru=ru, lam=lam, s_hat=sh)
+
+
+def oracle_naive(p, K, alpha=ALPHA, beta=BETA):
+    st = o_accel.init_state(p.I, p.J)
+    rh, ru, lam = o_naive.run(p.x, p.a, p.Rp, p.b, *st, K, alpha, beta)
+    sh = o_extract.s_hat(p.x, p.a, p.Rp, p.b, rh, ru, lam)
+    return dict(rh=rh, ru=ru, lam=lam, s_hat=sh)
+
+
+def errors(gpu, ref):
+    return {k: nrel(gpu[k], ref[k]) for k in ("rh", "ru", "lam", "s_hat") if k in gpu}
+
+
+def assert_close(gpu, ref, tol=TOL, what=""):
+    e = errors(gpu, ref)
+    bad = {k: v for k, v in e.items() if not (v <= tol)}
+    assert not bad, f"{what} normwise relative errors above {tol}: {e}"
+    return e
