@@ -1,18 +1,326 @@
-// Adjoint of the accelerated forward path (filled in below).
+// Adjoint of the differentiable path: K accelerated iterations (Algorithm 2)
+// from (r^h_0, r^u_0, lambda_0), the Wiener-filter extraction
+// s_hat = gamma rho^ax at the final state, and the per-bin precomputation of
+// tau^ax, sigma^bx, nu from x.
+//
+// Complex adjoints follow torch's convention z_bar = dL/dRe z + i dL/dIm z:
+//   z = c w (c const)    -> w_bar += conj(c) z_bar
+//   r = |z|^2            -> z_bar += 2 z r_bar
+//   z = r w (r real)     -> w_bar += r z_bar,  r_bar += Re(conj(w) z_bar)
+//
+// One workgroup per row (the RESIDENT layout of the forward), bins in
+// registers.  For k = K-1 .. 0 the iteration is recomputed from the
+// checkpoint theta_k and reversed.  lambda couples the bins of a row twice
+// per iteration, so each reversed iteration needs two frame sums:
+//   #1: d lambda_{k+1}/d(everything after it) through r^u_{k+1}
+//       (r^u uses the new lambda): sum_j u_bar_j/M (|e_j|^2 + |s_ab|^2 g_j u_j);
+//       it completes lambda_bar_{k+1}, which reaches every bin through
+//       lambda_{k+1} = mean_j t_j.
+//   #2: d/d lambda_k of everything computed from it in this iteration.
+// At the end x_bar = c tau_bar' + b sigma_bar + 2 nu_bar (R')^+ x with
+// c = (R')^+ a and tau_bar' = tau_bar - 2 tau^ax nu_bar / tau^aa (nu =
+// tau^xx - |tau^ax|^2/tau^aa), in FP64 from the row constants.
 #include "accel_common.h"
 
 namespace rcscm {
+
+namespace {
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, uint64_t (*red)[NT / 64], int& phase) {
+  LamAcc<0> a;
+  a.s = v;
+  a = wave_allreduce<0>(a);
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) red[phase & 1][t >> 6] = a.pack();
+  __syncthreads();
+  const double s = wave_sum_packed<0>(red[phase & 1], NT / 64).s;
+  ++phase;
+  return s;
+}
+
+template <int NT, int BPL>
+__global__ __launch_bounds__(NT) void backward_kernel(
+    const int* __restrict__ row_list, const RowInfo* __restrict__ rows,
+    const RowConstF* __restrict__ rcf, const RowConstD* __restrict__ rcd,
+    const float2* __restrict__ x, const float4* __restrict__ tsig, const float* __restrict__ nu,
+    const float* __restrict__ ck_rh, const float* __restrict__ ck_ru,
+    const float* __restrict__ ck_lam, long long sb, int sr, const float* __restrict__ rh_fin,
+    const float* __restrict__ ru_fin, const float* __restrict__ lam_fin, int K, float inv_a2,
+    const float2* __restrict__ grad_s, float2* __restrict__ grad_x, float* __restrict__ grad_rh0,
+    float* __restrict__ grad_lam0) {
+  const int row = row_list[blockIdx.x];
+  const RowInfo ri = rows[row];
+  const RowConstF rc = rcf[row];
+  const int J = ri.J;
+  const long long base = ri.bin_off;
+  const int t = threadIdx.x;
+  const float S2 = rc.sab2, sr_ = rc.sab_re, si_ = rc.sab_im, taa = rc.t_aa;
+  const float invM = rc.invM;
+  __shared__ uint64_t red[2][NT / 64];
+  int phase = 0;
+
+  float4 ts[BPL];
+  float Tbr[BPL], Tbi[BPL], Bbr[BPL], Bbi[BPL], nub[BPL], hb[BPL], ub[BPL];
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * NT;
+    ts[q] = (j < J) ? tsig[base + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    Tbr[q] = Tbi[q] = Bbr[q] = Bbi[q] = nub[q] = hb[q] = ub[q] = 0.f;
+  }
+
+  // ---- extraction: s_hat = gamma P, P = T + s B / lambda, gamma = h / (u + h A)
+  float lam_bar;
+  {
+    const float lam = lam_fin[row];
+    const float il = 1.0f / lam;
+    const float A = fmaf(S2, il, taa);
+    double c = 0.0;
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      const int j = t + q * NT;
+      if (j >= J) continue;
+      const float h = rh_fin[base + j], u = ru_fin[base + j];
+      const float2 gs = grad_s[base + j];
+      const float4 T = ts[q];
+      const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
+      const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
+      const float D = fmaf(h, A, u);
+      const float gam = h / D;
+      const float gbar = Pr * gs.x + Pi * gs.y;
+      const float Pbr = gam * gs.x, Pbi = gam * gs.y;
+      const float Dbar = -gbar * gam / D;
+      hb[q] = gbar / D + Dbar * A;
+      ub[q] = Dbar;
+      const float Abar = Dbar * h;
+      Tbr[q] += Pbr;
+      Tbi[q] += Pbi;
+      // B_bar += conj(s) il P_bar
+      Bbr[q] += il * (sr_ * Pbr + si_ * Pbi);
+      Bbi[q] += il * (sr_ * Pbi - si_ * Pbr);
+      // il_bar += Re(conj(s B) P_bar)
+      const float sBr = sr_ * T.z - si_ * T.w, sBi = sr_ * T.w + si_ * T.z;
+      c += (double)(sBr * Pbr + sBi * Pbi) + (double)(S2 * Abar);
+    }
+    const double ilbar = block_sum<NT>(c, red, phase);
+    lam_bar = (float)(-(double)il * (double)il * ilbar);
+  }
+
+  // ---- iterations, last to first
+  for (int k = K - 1; k >= 0; --k) {
+    const float lam = ck_lam[(long long)k * sr + row];
+    const float lam_n = (k + 1 < K) ? ck_lam[(long long)(k + 1) * sr + row] : lam_fin[row];
+    const float il = 1.0f / lam, il_n = 1.0f / lam_n;
+    const float A = fmaf(S2, il, taa), A_n = fmaf(S2, il_n, taa);
+    float vh[BPL], vu[BPL];
+    double c1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      const int j = t + q * NT;
+      const bool on = j < J;
+      vh[q] = on ? ck_rh[(long long)k * sb + base + j] : 1.f;
+      vu[q] = on ? ck_ru[(long long)k * sb + base + j] : 1.f;
+      const float4 T = ts[q];
+      const float h = vh[q], u = vu[q];
+      const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
+      const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
+      const float D = fmaf(h, A, u);
+      const float g = h / D;
+      const float wr = g * Pr, wi = g * Pi;
+      const float er = T.z - (sr_ * wr + si_ * wi), ei = T.w - (sr_ * wi - si_ * wr);
+      const float E = er * er + ei * ei;
+      if (on) c1 += (double)(ub[q] * invM * fmaf(S2, g * u, E));
+    }
+    const double ilnbar = block_sum<NT>(c1, red, phase);
+    const float lam_n_bar = (float)((double)lam_bar - (double)il_n * (double)il_n * ilnbar);
+    const float tbar = lam_n_bar * rc.invJ;
+
+    double c2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      const int j = t + q * NT;
+      const float4 T = ts[q];
+      const float h = vh[q], u = vu[q];
+      const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
+      const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
+      const float D = fmaf(h, A, u);
+      const float g = h / D;
+      const float R2 = Pr * Pr + Pi * Pi;
+      const float Q = fmaf(g, R2, u);
+      const float wr = g * Pr, wi = g * Pi;
+      const float er = T.z - (sr_ * wr + si_ * wi), ei = T.w - (sr_ * wi - si_ * wr);
+      const float E = er * er + ei * ei;
+      const float dr = T.x - wr * taa, di = T.y - wi * taa;
+      // r^u_{k+1} = (g u A_n + nu + |d|^2 / taa + E / lambda_n) / M
+      const float uu = ub[q] * invM;
+      float gbar = uu * u * A_n;
+      float ubar = uu * g * A_n;
+      nub[q] += uu;
+      const float dsc = 2.0f * uu * rc.inv_t_aa;
+      const float dbr = dsc * dr, dbi = dsc * di;
+      float Ebar = uu * il_n;
+      // lambda_{k+1} = mean_j (g S2 + E / u)
+      gbar += S2 * tbar;
+      Ebar += tbar / u;
+      ubar -= E / (u * u) * tbar;
+      // d = T - w taa
+      Tbr[q] += dbr;
+      Tbi[q] += dbi;
+      float wbr = -taa * dbr, wbi = -taa * dbi;
+      // E = |e|^2 ; e = B - conj(s) w
+      const float ebr = 2.0f * er * Ebar, ebi = 2.0f * ei * Ebar;
+      Bbr[q] += ebr;
+      Bbi[q] += ebi;
+      wbr -= sr_ * ebr - si_ * ebi;
+      wbi -= sr_ * ebi + si_ * ebr;
+      // w = g P
+      gbar += Pr * wbr + Pi * wbi;
+      float Pbr = g * wbr, Pbi = g * wbi;
+      // h_{k+1} = g Q / (alpha + 2) + beta / (alpha + 2)
+      const float hp = hb[q] * inv_a2;
+      gbar += hp * Q;
+      const float Qbar = hp * g;
+      // Q = u + g R2 ; R2 = |P|^2
+      ubar += Qbar;
+      gbar += Qbar * R2;
+      Pbr += 2.0f * Pr * (Qbar * g);
+      Pbi += 2.0f * Pi * (Qbar * g);
+      // g = h / D ; D = u + h A
+      float hbar = gbar / D;
+      const float Dbar = -gbar * g / D;
+      ubar += Dbar;
+      hbar += Dbar * A;
+      // P = T + s B il
+      Tbr[q] += Pbr;
+      Tbi[q] += Pbi;
+      Bbr[q] += il * (sr_ * Pbr + si_ * Pbi);
+      Bbi[q] += il * (sr_ * Pbi - si_ * Pbr);
+      const float sBr = sr_ * T.z - si_ * T.w, sBi = sr_ * T.w + si_ * T.z;
+      if (j < J) c2 += (double)(sBr * Pbr + sBi * Pbi) + (double)(S2 * Dbar * h);
+      hb[q] = hbar;
+      ub[q] = ubar;
+    }
+    const double ilbar = block_sum<NT>(c2, red, phase);
+    lam_bar = (float)(-(double)il * (double)il * ilbar);
+  }
+
+  if (t == 0 && grad_lam0 != nullptr) grad_lam0[row] = lam_bar;
+
+  // ---- precomputation: x_bar = c T_bar' + b B_bar + 2 nu_bar (R')^+ x
+  const RowConstD* Dc = rcd + row;
+  const int M = ri.M;
+  const double taad = Dc->t_aa;
+  const double inv_taad = taad > 0.0 ? 1.0 / taad : 0.0;
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * NT;
+    if (j >= J) continue;
+    if (grad_rh0 != nullptr) grad_rh0[base + j] = hb[q];
+    if (grad_x == nullptr) continue;
+    const float4 T = ts[q];
+    const double nb = nub[q];
+    const double tr = (double)Tbr[q] - 2.0 * (double)T.x * nb * inv_taad;
+    const double ti = (double)Tbi[q] - 2.0 * (double)T.y * nb * inv_taad;
+    const float2* xp = x + ri.x_off + (long long)j * M;
+    double xr[MAXM], xi[MAXM], zr[MAXM], zi[MAXM];
+#pragma unroll
+    for (int m = 0; m < MAXM; ++m) {
+      const float2 v = (m < M) ? xp[m] : make_float2(0.f, 0.f);
+      xr[m] = v.x;
+      xi[m] = v.y;
+    }
+#pragma unroll
+    for (int p = 0; p < MAXM; ++p) {  // z = G x
+      double ar = 0.0, ai = 0.0;
+      if (p < M) {
+#pragma unroll
+        for (int n = 0; n < MAXM; ++n) {
+          if (n < M) {
+            const double2 G = Dc->G[p * MAXM + n];
+            ar = fma(G.x, xr[n], fma(-G.y, xi[n], ar));
+            ai = fma(G.x, xi[n], fma(G.y, xr[n], ai));
+          }
+        }
+      }
+      zr[p] = ar;
+      zi[p] = ai;
+    }
+    float2* gp = grad_x + ri.x_off + (long long)j * M;
+#pragma unroll
+    for (int m = 0; m < MAXM; ++m) {
+      if (m >= M) continue;
+      // ((R')^+ x)_m = sum_p conj(G[p][m]) z_p
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int p = 0; p < MAXM; ++p) {
+        if (p < M) {
+          const double2 G = Dc->G[p * MAXM + m];
+          yr = fma(G.x, zr[p], fma(G.y, zi[p], yr));
+          yi = fma(G.x, zi[p], fma(-G.y, zr[p], yi));
+        }
+      }
+      const double2 c = Dc->c[m];
+      const double2 b = Dc->b[m];
+      const double gr = c.x * tr - c.y * ti + b.x * Bbr[q] - b.y * Bbi[q] + 2.0 * nb * yr;
+      const double gi = c.x * ti + c.y * tr + b.x * Bbi[q] + b.y * Bbr[q] + 2.0 * nb * yi;
+      gp[m] = make_float2((float)gr, (float)gi);
+    }
+  }
+}
+
+template <int NT, int BPL>
+void bw_launch(hipStream_t s, int nrows, const int* row_list, const RowInfo* rows,
+               const RowConstF* rcf, const RowConstD* rcd, const float2* x, const float4* tsig,
+               const float* nu, const float* ck_rh, const float* ck_ru, const float* ck_lam,
+               long long sb, int sr, const float* rh_fin, const float* ru_fin,
+               const float* lam_fin, int K, float inv_a2, const float2* grad_s, float2* grad_x,
+               float* grad_rh0, float* grad_lam0) {
+  hipLaunchKernelGGL((backward_kernel<NT, BPL>), dim3(nrows), dim3(NT), 0, s, row_list, rows, rcf,
+                     rcd, x, tsig, nu, ck_rh, ck_ru, ck_lam, sb, sr, rh_fin, ru_fin, lam_fin, K,
+                     inv_a2, grad_s, grad_x, grad_rh0, grad_lam0);
+}
+
+using BwFn = void (*)(hipStream_t, int, const int*, const RowInfo*, const RowConstF*,
+                      const RowConstD*, const float2*, const float4*, const float*, const float*,
+                      const float*, const float*, long long, int, const float*, const float*,
+                      const float*, int, float, const float2*, float2*, float*, float*);
+
+#define RCSCM_BW_LIST(NT)                                                                   \
+  {bw_launch<NT, 1>, bw_launch<NT, 2>, bw_launch<NT, 3>, bw_launch<NT, 4>, bw_launch<NT, 5>, \
+   bw_launch<NT, 6>, bw_launch<NT, 7>, bw_launch<NT, 8>, nullptr, bw_launch<NT, 10>, nullptr, \
+   bw_launch<NT, 12>, nullptr, nullptr, nullptr, bw_launch<NT, 16>}
+#define RCSCM_BW_LIST_1024                                                                  \
+  {bw_launch<1024, 1>, bw_launch<1024, 2>, bw_launch<1024, 3>, bw_launch<1024, 4>,          \
+   bw_launch<1024, 5>, bw_launch<1024, 6>, bw_launch<1024, 7>, bw_launch<1024, 8>, nullptr, \
+   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}
+
+const BwFn kBw[5][16] = {RCSCM_BW_LIST(64), RCSCM_BW_LIST(128), RCSCM_BW_LIST(256),
+                         RCSCM_BW_LIST(512), RCSCM_BW_LIST_1024};
+
+}  // namespace
 
 void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_list,
                      const RowInfo* rows, const RowConstF* rcf, const RowConstD* rcd,
                      const float2* x, const float4* tsig, const float* nu, const float* ckpt_rh,
                      const float* ckpt_ru, const float* ckpt_lam, long long ckpt_stride_bins,
-                     int ckpt_stride_rows, int K, float alpha, float beta, const float2* grad_s,
-                     float2* grad_x, float* grad_rh0, float* grad_lam0, unsigned* status) {
-  (void)s; (void)nt; (void)bpl; (void)nrows; (void)row_list; (void)rows; (void)rcf; (void)rcd;
-  (void)x; (void)tsig; (void)nu; (void)ckpt_rh; (void)ckpt_ru; (void)ckpt_lam;
-  (void)ckpt_stride_bins; (void)ckpt_stride_rows; (void)K; (void)alpha; (void)beta; (void)grad_s;
-  (void)grad_x; (void)grad_rh0; (void)grad_lam0; (void)status;
+                     int ckpt_stride_rows, const float* rh_fin, const float* ru_fin,
+                     const float* lam_fin, int K, float alpha, const float2* grad_s,
+                     float2* grad_x, float* grad_rh0, float* grad_lam0) {
+  if (nrows <= 0) return;
+  int ni = -1;
+  switch (nt) {
+    case 64: ni = 0; break;
+    case 128: ni = 1; break;
+    case 256: ni = 2; break;
+    case 512: ni = 3; break;
+    case 1024: ni = 4; break;
+    default: return;
+  }
+  if (bpl < 1 || bpl > 16 || kBw[ni][bpl - 1] == nullptr) return;
+  const float inv_a2 = (float)(1.0 / ((double)alpha + 2.0));
+  kBw[ni][bpl - 1](s, nrows, row_list, rows, rcf, rcd, x, tsig, nu, ckpt_rh, ckpt_ru, ckpt_lam,
+                   ckpt_stride_bins, ckpt_stride_rows, rh_fin, ru_fin, lam_fin, K, inv_a2, grad_s,
+                   grad_x, grad_rh0, grad_lam0);
 }
 
 }  // namespace rcscm

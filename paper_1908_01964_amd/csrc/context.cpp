@@ -652,13 +652,13 @@ rcscm_status rcscm_backward(rcscm_ctx* c, const void* x, const void* grad_s_hat,
   if (!(c->p.flags & RCSCM_FLAG_CHECKPOINT) || c->ck_K < 0)
     return c->fail(RCSCM_ESTATE, "backward needs a context with checkpoints that was iterated");
   if (!x || !grad_s_hat) return c->fail(RCSCM_EINVAL, "x and grad_s_hat must not be NULL");
-  return c->fail(RCSCM_ESTATE, "backward is not built yet");
   for (const auto& cl : c->res_classes) {
     launch_backward(c->stream, c->res_nt, cl.bpl, cl.count, c->d_row_list + cl.offset, c->d_rows,
                     c->d_rcf, c->d_rcd, static_cast<const float2*>(x), c->d_tsig, c->d_nu,
-                    c->d_ck_rh, c->d_ck_ru, c->d_ck_lam, c->nbins, c->nrows, c->ck_K,
-                    (float)c->p.alpha, (float)c->p.beta, static_cast<const float2*>(grad_s_hat),
-                    static_cast<float2*>(grad_x), grad_rh0, grad_lam0, c->d_status);
+                    c->d_ck_rh, c->d_ck_ru, c->d_ck_lam, c->nbins, c->nrows, c->d_rh, c->d_ru,
+                    c->d_lam[c->lam_cur], c->ck_K, (float)c->p.alpha,
+                    static_cast<const float2*>(grad_s_hat), static_cast<float2*>(grad_x),
+                    grad_rh0, grad_lam0);
     RCSCM_HIP(c, hipGetLastError());
   }
   return RCSCM_OK;

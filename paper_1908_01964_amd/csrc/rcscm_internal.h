@@ -121,10 +121,10 @@ void launch_naive_b(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
 // Adjoint of the RESIDENT/STREAM accelerated forward (checkpointed).
 void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_list,
                      const RowInfo* rows, const RowConstF* rcf, const RowConstD* rcd,
-                     const float2* x, const float4* tsig, const float* nu,
-                     const float* ckpt_rh, const float* ckpt_ru, const float* ckpt_lam,
-                     long long ckpt_stride_bins, int ckpt_stride_rows, int K, float alpha,
-                     float beta, const float2* grad_s, float2* grad_x, float* grad_rh0,
-                     float* grad_lam0, unsigned* status);
+                     const float2* x, const float4* tsig, const float* nu, const float* ckpt_rh,
+                     const float* ckpt_ru, const float* ckpt_lam, long long ckpt_stride_bins,
+                     int ckpt_stride_rows, const float* rh_fin, const float* ru_fin,
+                     const float* lam_fin, int K, float alpha, const float2* grad_s,
+                     float2* grad_x, float* grad_rh0, float* grad_lam0);
 
 }  // namespace rcscm
