@@ -95,10 +95,14 @@ def cpu_baseline(I, J, K, reps, cores):
     walls = []
     ref = None
     with ctx.Pool(cores) as pool:
-        for r in range(reps):
+        r = 0
+        cpu_s = 0.0
+        while (reps and r < reps) or (not reps and (r < 3 or cpu_s < 10.0)):
+            r += 1
             t0 = time.perf_counter()
             res = pool.map(_oracle_rows, [(b, K, False) for b in blocks])
             walls.append(time.perf_counter() - t0)
+            cpu_s += walls[-1] * cores
             if ref is None:
                 ref = dict(rh=np.zeros((I, J)), ru=np.zeros((I, J)), lam=np.zeros(I),
                            s_hat=np.zeros((I, J), np.complex128))
@@ -120,7 +124,7 @@ def cpu_baseline(I, J, K, reps, cores):
         "value": acc_rate, "unit": "TF-bin updates/s", "cores": cores, "kind": "oracle",
         "sample": (f"the full workload (I={I}, J={J}, K={K}), FP64 numpy oracle of the "
                    f"second-stage rule incl. precompute and extraction, rows split over "
-                   f"{cores} processes x 1 thread, median of {reps} runs "
+                   f"{cores} processes x 1 thread, median of {len(walls)} runs "
                    f"({t:.2f} s each); naive-rule rate scaled from {len(sample)} rows "
                    f"timed in the same workers ({wall_n:.1f} s)"),
         "naive_value": naive_rate,
@@ -161,16 +165,36 @@ def time_steps(ctx, inputs, out, K, steps, warmup, torch):
     return wall, phases
 
 
+def load_workload(wid):
+    """(I, Js, Ms, K, problems, label) of a named workload."""
+    from synth import CONFIGS, batch_shapes, batch_utterance, config
+    c = CONFIGS[wid]
+    if wid == 2:
+        Js, Ms = batch_shapes()
+        probs = [batch_utterance(u) for u in range(len(Js))]
+        label = (f"ragged batch of {len(Js)} utterances, J in [{min(Js)}, {max(Js)}], "
+                 f"M in {{2,4,6}}, I=513, K=20")
+        return c["I"], Js, Ms, c["K"], probs, label
+    p = config(wid, with_truth=False)
+    label = {1: "sinc-coherence M=4 I=513 J=1000 K=20, one utterance",
+             4: "sinc-coherence M=8 I=1025 J=8000 K=30, one utterance"}[wid]
+    return p.I, [p.J], [p.M], c["K"], [p], label
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", type=int, default=1, choices=[1, 2, 4],
+                    help="1 = the bench line (M=4, I=513, J=1000, K=20); 2 = ragged batch; "
+                         "4 = large instance")
     ap.add_argument("--schedule", default="auto", choices=["auto", "resident", "stream"])
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--block", type=int, default=-1)
+    ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--naive-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=5)
+    ap.add_argument("--cpu-reps", type=int, default=0, help="0 = enough runs for >= 10 s of CPU work")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the estimation is independent per frequency row and "
@@ -180,81 +204,88 @@ def main():
 
     import numpy as np
 
-    from synth import CONFIGS, config
+    from synth import CONFIGS
 
-    I, J, M, K = (CONFIGS[1][k] for k in ("I", "J", "M", "K"))
     cb, ref = None, None
-    if not args.no_cpu_baseline:
+    if args.workload == 1 and not args.no_cpu_baseline:
         # before any GPU work: the worker processes are started from a process that has not
         # touched the GPU
+        c1 = CONFIGS[1]
         cores = min(16, os.cpu_count() or 1)
-        cb, ref = cpu_baseline(I, J, K, args.cpu_reps, cores)
+        cb, ref = cpu_baseline(c1["I"], c1["J"], c1["K"], args.cpu_reps, cores)
+
+    I, Js, Ms, K, probs, label = load_workload(args.workload)
 
     import torch
 
     from paper_1908_01964_amd import Context, to_device
     from paper_1908_01964_amd.autotune import best_params
 
-    p = config(1, with_truth=False)
-    inputs = to_device(p)
+    inputs = to_device(probs)
+    del probs
     dev = inputs[0].device
-    tuned = best_params(I, [J], [M], K) if (args.schedule == "auto" and not args.block) else {}
+    tuned = best_params(I, Js, Ms, K) if (args.schedule == "auto" and args.block < 0) else {}
     sched = dict(schedule=args.schedule if args.schedule != "auto" else tuned.get("schedule", "auto"),
-                 block=args.block or tuned.get("block", 0), chunk=tuned.get("chunk", 0))
-    ctx = Context.single(I, J, M, **sched)
-    out = dict(rh=torch.empty(I * J, dtype=torch.float32, device=dev),
-               ru=torch.empty(I * J, dtype=torch.float32, device=dev),
-               lam=torch.empty(I, dtype=torch.float32, device=dev),
-               s_hat=torch.empty(I * J, dtype=torch.complex64, device=dev))
+                 block=args.block if args.block >= 0 else tuned.get("block", 0),
+                 chunk=args.chunk or tuned.get("chunk", 0), graph=bool(tuned.get("graph", True)))
+    nbins = I * sum(Js)
+    ctx = Context(I, Js, Ms, **sched)
+    out = dict(rh=torch.empty(nbins, dtype=torch.float32, device=dev),
+               ru=torch.empty(nbins, dtype=torch.float32, device=dev),
+               lam=torch.empty(I * len(Js), dtype=torch.float32, device=dev),
+               s_hat=torch.empty(nbins, dtype=torch.complex64, device=dev))
     wall, phases = time_steps(ctx, inputs, out, K, args.steps, args.warmup, torch)
     ctx.sync()
     used = ctx.schedule()
-    updates = I * J * K
+    updates = nbins * K
     value = updates * args.steps / wall
-    gpu_out = {k: v.cpu().numpy() for k, v in out.items()}
+    gpu_out = {k: v.cpu().numpy() for k, v in out.items()} if ref is not None else None
     ctx.close()
 
-    # naive rule, same workload and step
-    ctxn = Context.single(I, J, M, rule="naive")
-    wall_n, phases_n = time_steps(ctxn, inputs, dict(out), K, args.naive_steps, 1, torch)
-    ctxn.sync()
-    ctxn.close()
-    naive_value = updates * args.naive_steps / wall_n
+    naive = None
+    if args.naive_steps > 0:
+        ctxn = Context(I, Js, Ms, rule="naive")
+        wall_n, phases_n = time_steps(ctxn, inputs, dict(out), K, args.naive_steps, 1, torch)
+        ctxn.sync()
+        ctxn.close()
+        naive = {"value": updates * args.naive_steps / wall_n,
+                 "ms_per_step": wall_n / args.naive_steps * 1e3, "phases_us": phases_n}
 
-    # roofline of the dominant kernel (one launch per iterate call)
+    # roofline of the dominant kernel
     it_us = phases["iterate"]
     if used["schedule"] == "resident":
         achieved = FLOPS_PER_UPDATE * updates / (it_us * 1e-6) / 1e12
-        traffic = load_traffic()
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                "traffic": traffic,
+                "traffic": load_traffic() if args.workload == 1 else None,
                 "kernel": "accel_resident_kernel", "launch_us": it_us,
                 "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": updates,
-                "effective_GBps_at_36B_per_update": STREAM_BYTES_PER_UPDATE * updates / (it_us * 1e-6) / 1e9,
-                "hbm_GBps_algorithmic": RESIDENT_BYTES_PER_BIN * I * J / (it_us * 1e-6) / 1e9}
+                "hbm_GBps_algorithmic": RESIDENT_BYTES_PER_BIN * nbins / (it_us * 1e-6) / 1e9,
+                "effective_GBps_at_36B_per_update":
+                    STREAM_BYTES_PER_UPDATE * updates / (it_us * 1e-6) / 1e9}
     else:
         launch_us = it_us / (K + 1)
-        achieved = STREAM_BYTES_PER_UPDATE * I * J / (launch_us * 1e-6) / 1e9
+        achieved = STREAM_BYTES_PER_UPDATE * nbins / (launch_us * 1e-6) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "accel_stream_kernel",
-                "launch_us": launch_us}
+                "launch_us": launch_us, "bytes_per_update": STREAM_BYTES_PER_UPDATE}
 
     line = {
         "metric": "TF-bin updates/s (M=4,I=513,J=1000) accel vs naive; % HBM peak; rel err vs FP64",
         "value": value, "unit": "TF-bin updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "sinc-coherence M=4 I=513 J=1000 K=20, one utterance",
-                   "M": M, "I": I, "J": J, "K": K, "schedule": used,
+        "config": {"workload": label, "I": I, "J": Js if len(Js) > 1 else Js[0],
+                   "M": Ms if len(Ms) > 1 else Ms[0], "K": K, "bins": nbins, "schedule": used,
                    "step": "init(setup+precompute)+iterate(K)+extract(s_hat)"},
         "phases_us": phases,
-        "naive": {"value": naive_value, "ms_per_step": wall_n / args.naive_steps * 1e3,
-                  "phases_us": phases_n},
-        "speedup_vs_naive": value / naive_value,
         "iterate_only_value": updates / (phases["iterate"] * 1e-6),
         "roofline": roof,
     }
+    if naive is not None:
+        line["naive"] = naive
+        line["speedup_vs_naive"] = value / naive["value"]
+        line["iterate_speedup_vs_naive"] = naive["phases_us"]["iterate"] / phases["iterate"]
     if cb is not None:
         line["cpu_baseline"] = cb
         errs = {}

@@ -54,6 +54,8 @@ def best_params(I: int, Js: Sequence[int], Ms: Sequence[int], K: int, tune_if_mi
 
 
 def _candidates(maxJ: int):
+    if maxJ <= 8192:
+        yield dict(schedule="resident", block=0, chunk=0)  # per-row workgroup sizes
     for b in RESIDENT_BLOCKS:
         cap = b * (8 if b == 1024 else 16)
         if maxJ <= cap:

@@ -55,7 +55,7 @@ struct rcscm_ctx {
   // chunk ranges per microphone count (chunks sorted by M in d_chunks_m)
   std::vector<std::pair<int, int>> m_range = std::vector<std::pair<int, int>>(RCSCM_MAX_M + 1, {0, 0});
   struct ResClass {
-    int bpl, count, offset;
+    int nt, bpl, count, offset;
   };
   std::vector<ResClass> res_classes;
 
@@ -237,10 +237,13 @@ static rcscm_status validate(int U, int I, const int* J, const int* M, const rcs
   return RCSCM_OK;
 }
 
-static int auto_block(int maxJ) {
-  // smallest workgroup that holds the longest row with at most 8 bins per lane
+// Workgroup size of a row in the RESIDENT schedule when params.block == 0:
+// the smallest workgroup that holds the row with at most 4 bins per lane
+// (1024 lanes for longer rows).  Per-row sizes keep short rows of a ragged
+// batch from idling most lanes of a wide workgroup.
+static int auto_block(int J) {
   for (int nt : {64, 128, 256, 512, 1024})
-    if (nt * 8 >= maxJ) return nt;
+    if (nt * 4 >= J) return nt;
   return 1024;
 }
 
@@ -308,23 +311,32 @@ static rcscm_status build_tables(rcscm_ctx* c) {
   } else {
     c->schedule = RCSCM_SCHED_STREAM;
   }
-  c->res_nt = c->p.block ? c->p.block : auto_block(maxJ);
   std::vector<int> row_list;
   c->res_classes.clear();
+  c->res_nt = c->p.block;
   if (c->p.rule == RCSCM_RULE_ACCEL && c->schedule == RCSCM_SCHED_RESIDENT) {
-    std::map<int, std::vector<int>> cls;
+    // classes of rows sharing (workgroup size, bins per lane): one launch each
+    std::map<std::pair<int, int>, std::vector<int>> cls;
     for (int r = 0; r < c->nrows; ++r) {
-      const int need = (c->h_rows[r].J + c->res_nt - 1) / c->res_nt;
-      int bpl = round_up_bpl(need);
-      while (bpl > 0 && !resident_supported(c->res_nt, bpl)) bpl = round_up_bpl(bpl + 1);
+      const int J = c->h_rows[r].J;
+      const int nt = c->p.block ? c->p.block : auto_block(J);
+      int bpl = round_up_bpl((J + nt - 1) / nt);
+      while (bpl > 0 && !resident_supported(nt, bpl)) bpl = round_up_bpl(bpl + 1);
       if (bpl < 0) return c->fail(RCSCM_ESHAPE, "row too long for the RESIDENT schedule");
-      cls[bpl].push_back(r);
+      cls[{nt, bpl}].push_back(r);
     }
-    for (auto& kv : cls) {
-      // longest rows first inside the launch order
-      rcscm_ctx::ResClass rc{kv.first, (int)kv.second.size(), (int)row_list.size()};
-      row_list.insert(row_list.end(), kv.second.begin(), kv.second.end());
+    long long best_bins = -1;
+    for (auto it = cls.rbegin(); it != cls.rend(); ++it) {  // widest rows first
+      rcscm_ctx::ResClass rc{it->first.first, it->first.second, (int)it->second.size(),
+                             (int)row_list.size()};
+      row_list.insert(row_list.end(), it->second.begin(), it->second.end());
       c->res_classes.push_back(rc);
+      long long bins = 0;
+      for (int r : it->second) bins += c->h_rows[r].J;
+      if (bins > best_bins) {
+        best_bins = bins;
+        c->res_nt = rc.nt;  // reported by rcscm_get_schedule: the class with most bins
+      }
     }
   }
   if (row_list.empty()) row_list.push_back(0);
@@ -531,7 +543,7 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
       c->ck_K = K;
     }
     for (const auto& cl : c->res_classes) {
-      launch_accel_resident(s, c->res_nt, cl.bpl, c->p.lamsum, cl.count, c->d_row_list + cl.offset,
+      launch_accel_resident(s, cl.nt, cl.bpl, c->p.lamsum, cl.count, c->d_row_list + cl.offset,
                             c->d_rows, c->d_rcf, c->d_tsig, c->d_nu, c->d_rh, c->d_ru,
                             c->d_lam[c->lam_cur], alpha, beta, K, ck_rh, ck_ru, ck_lam, c->nbins,
                             c->nrows, c->d_status);
@@ -653,7 +665,7 @@ rcscm_status rcscm_backward(rcscm_ctx* c, const void* x, const void* grad_s_hat,
     return c->fail(RCSCM_ESTATE, "backward needs a context with checkpoints that was iterated");
   if (!x || !grad_s_hat) return c->fail(RCSCM_EINVAL, "x and grad_s_hat must not be NULL");
   for (const auto& cl : c->res_classes) {
-    launch_backward(c->stream, c->res_nt, cl.bpl, cl.count, c->d_row_list + cl.offset, c->d_rows,
+    launch_backward(c->stream, cl.nt, cl.bpl, cl.count, c->d_row_list + cl.offset, c->d_rows,
                     c->d_rcf, c->d_rcd, static_cast<const float2*>(x), c->d_tsig, c->d_nu,
                     c->d_ck_rh, c->d_ck_ru, c->d_ck_lam, c->nbins, c->nrows, c->d_rh, c->d_ru,
                     c->d_lam[c->lam_cur], c->ck_K, (float)c->p.alpha,

@@ -1,0 +1,99 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared function,
+and rejects bad arguments on the host before any device work."""
+import ctypes
+
+import pytest
+
+import paper_1908_01964_amd as pkg
+from paper_1908_01964_amd import rcscm as R
+
+
+def test_library_exports_every_declared_function():
+    L = pkg.lib()
+    names = pkg.header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.rcscm_version() == 1
+
+
+def test_default_params_follow_table2():
+    p = pkg.default_params()
+    assert p.alpha == pytest.approx(1.1) and p.beta == pytest.approx(1e-16)
+    assert (p.rh0, p.ru0, p.lam0) == (1.0, 1.0, 1.0)
+    assert p.rule == R.RULES["accel"] and p.schedule == R.SCHEDULES["auto"]
+    assert p.lamsum == R.LAMSUMS["f64"] and p.flags == 0
+
+
+def _create(I=4, J=16, M=4, **kw):
+    p = R._params(**kw)
+    h = ctypes.c_void_p()
+    st = pkg.lib().rcscm_create(ctypes.byref(h), I, J, M, ctypes.byref(p), None)
+    return st, pkg.lib().rcscm_last_error(None).decode()
+
+
+@pytest.mark.parametrize("kw,status,msg", [
+    (dict(I=0), R.ESHAPE, "I must"),
+    (dict(J=0), R.ESHAPE, "J must"),
+    (dict(M=1), R.ESHAPE, "M must"),
+    (dict(M=9), R.ESHAPE, "M must"),
+    (dict(alpha=-2.5), R.EINVAL, "alpha"),
+    (dict(alpha=float("nan")), R.EINVAL, "alpha"),
+    (dict(beta=-1.0), R.EINVAL, "beta"),
+    (dict(rh0=0.0), R.EINVAL, "initial"),
+    (dict(lam0=float("inf")), R.EINVAL, "initial"),
+    (dict(rule=7), R.EINVAL, "rule"),
+    (dict(schedule=9), R.EINVAL, "schedule"),
+    (dict(lamsum=3), R.EINVAL, "lamsum"),
+    (dict(block=100), R.EINVAL, "block"),
+    (dict(chunk=300), R.EINVAL, "chunk"),
+    (dict(J=20000, schedule="resident", block=1024), R.ESHAPE, "RESIDENT"),
+    (dict(J=5000, checkpoint=True, block=256), R.ESHAPE, "RESIDENT"),
+    (dict(rule="naive", checkpoint=True), R.EINVAL, "checkpoints"),
+])
+def test_create_rejects_bad_arguments_on_host(kw, status, msg):
+    st, err = _create(**kw)
+    assert st == status and msg in err
+
+
+def test_batch_argument_checks():
+    L = pkg.lib()
+    h = ctypes.c_void_p()
+    assert L.rcscm_create_batch(ctypes.byref(h), 2, 4, None, None, None, None) == R.EINVAL
+    J = (ctypes.c_int * 2)(10, 0)
+    M = (ctypes.c_int * 2)(4, 4)
+    assert L.rcscm_create_batch(ctypes.byref(h), 2, 4, J, M, None, None) == R.ESHAPE
+    assert "utterance 1" in L.rcscm_last_error(None).decode()
+    assert L.rcscm_create_batch(ctypes.byref(h), 0, 4, J, M, None, None) == R.ESHAPE
+    assert L.rcscm_create(None, 4, 4, 4, None, None) == R.EINVAL
+
+
+def test_null_context_calls():
+    L = pkg.lib()
+    assert L.rcscm_iterate(None, 1) == R.EINVAL
+    assert L.rcscm_init(None, None, None, None, None, None, None, None) == R.EINVAL
+    assert L.rcscm_extract(None, None, None, None, None) == R.EINVAL
+    assert L.rcscm_sync(None) == R.EINVAL
+    assert L.rcscm_set_state(None, None, None, None) == R.EINVAL
+    assert L.rcscm_backward(None, None, None, None, None, None) == R.EINVAL
+    v = ctypes.c_double()
+    assert L.rcscm_objective(None, ctypes.byref(v)) == R.EINVAL
+    L.rcscm_destroy(None)
+
+
+def test_workspace_bytes():
+    w1 = pkg.workspace_bytes(513, [1000], [4])
+    # per bin at least tau/sigma (16) + nu (4) + r^h, r^u (8)
+    assert w1 >= 513 * 1000 * 28
+    wn = pkg.workspace_bytes(513, [1000], [4], rule="naive")
+    assert wn >= w1 + 513 * 1000 * 16 * 4  # packed U^ (M^2 floats per bin)
+    assert pkg.workspace_bytes(513, [0], [4]) == 0
+    wb = pkg.workspace_bytes(8, [100, 300], [2, 6])
+    assert wb > pkg.workspace_bytes(8, [100], [2])
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(R, "_lib", None)
+    monkeypatch.setattr(R, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        R.lib()
