@@ -62,6 +62,7 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
   }
   float lam_t = lam[row];
   __shared__ uint64_t red[2][NW];
+  LamTerms Lt = lam_terms(rc, lam_t);
 
   for (int k = 0; k < K; ++k) {
     if (ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
@@ -75,7 +76,6 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
       }
       if (t == 0) ck_lam[(long long)k * ck_sr + row] = lam_t;
     }
-    const LamTerms Lt = lam_terms(rc, lam_t);
     LamAcc<LS> acc;
     PhaseA A[BPL];
 #pragma unroll
@@ -87,11 +87,12 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
     acc = wave_allreduce<LS>(acc);
     if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
     __syncthreads();
-    const float lam_n = wave_sum_packed<LS>(red[k & 1], NW).mean(invJ);
+    const float lam_n = slots_sum<LS, NW>(red[k & 1]).mean(invJ);
     const LamTerms Ln = lam_terms(rc, lam_n);
 #pragma unroll
     for (int q = 0; q < BPL; ++q) vru[q] = phase_b(ts[q], vnu[q], A[q], rc, Ln);
     lam_t = lam_n;
+    Lt = Ln;
   }
 
   bool bad = false;
@@ -232,12 +233,7 @@ __global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
     acc = wave_allreduce<LS>(acc);
     if ((t & 63) == 0) red[wave] = acc.pack();
     __syncthreads();
-    if (t == 0) {
-      LamAcc<LS> tot;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) tot.combine(LamAcc<LS>::unpack(red[w]));
-      part_out[ck.part] = tot.pack();
-    }
+    if (t == 0) part_out[ck.part] = slots_sum<LS, NW>(red).pack();
   }
 }
 
@@ -282,7 +278,8 @@ __global__ __launch_bounds__(256) void extract_kernel(
   const float lam = lam_in[ck.row];
   const LamTerms L = lam_terms(rc, lam);
   if (lam_out != nullptr && ck.start == 0 && threadIdx.x == 0) lam_out[ck.row] = lam;
-  for (int jj = threadIdx.x; jj < ck.len; jj += blockDim.x) {
+#pragma unroll 4
+  for (int jj = threadIdx.x; jj < ck.len; jj += 256) {
     const long long bin = ri.bin_off + ck.start + jj;
     const float vrh = rh_in[bin], vru = ru_in[bin];
     if (rh_out != nullptr) rh_out[bin] = vrh;

@@ -153,13 +153,96 @@ struct LamAcc<1> {
   }
 };
 
-// Butterfly over the 64 lanes of a wave, then lane 0's value for everyone
-// (the same association order in every wave of every workgroup).
+// ---- cross-lane sums ---------------------------------------------------------
+// Rotations inside each 16-lane row by 8, 4, 2, 1 (DPP row_ror, ALU-only, no
+// LDS round trip) leave the row sum in every lane of the row; the four row
+// sums are then read from lanes 0, 16, 32, 48 (readlane) and added in that
+// fixed order, so every lane of every wave gets the bitwise same value.
+// All 64 lanes must be active.
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = dpp_i32<CTRL>(__double2loint(v));
+  const int hi = dpp_i32<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float readlane_f32(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+constexpr int kRowRor8 = 0x128, kRowRor4 = 0x124, kRowRor2 = 0x122, kRowRor1 = 0x121;
+
+template <int LS, int CTRL>
+__device__ __forceinline__ LamAcc<LS> rot(const LamAcc<LS>& a);
+
+template <>
+__device__ __forceinline__ LamAcc<0> rot<0, kRowRor8>(const LamAcc<0>& a) { LamAcc<0> r; r.s = dpp_f64<kRowRor8>(a.s); return r; }
+template <>
+__device__ __forceinline__ LamAcc<0> rot<0, kRowRor4>(const LamAcc<0>& a) { LamAcc<0> r; r.s = dpp_f64<kRowRor4>(a.s); return r; }
+template <>
+__device__ __forceinline__ LamAcc<0> rot<0, kRowRor2>(const LamAcc<0>& a) { LamAcc<0> r; r.s = dpp_f64<kRowRor2>(a.s); return r; }
+template <>
+__device__ __forceinline__ LamAcc<0> rot<0, kRowRor1>(const LamAcc<0>& a) { LamAcc<0> r; r.s = dpp_f64<kRowRor1>(a.s); return r; }
+template <int CTRL>
+__device__ __forceinline__ LamAcc<1> rot1(const LamAcc<1>& a) {
+  LamAcc<1> r;
+  r.s = dpp_f32<CTRL>(a.s);
+  r.c = dpp_f32<CTRL>(a.c);
+  return r;
+}
+template <>
+__device__ __forceinline__ LamAcc<1> rot<1, kRowRor8>(const LamAcc<1>& a) { return rot1<kRowRor8>(a); }
+template <>
+__device__ __forceinline__ LamAcc<1> rot<1, kRowRor4>(const LamAcc<1>& a) { return rot1<kRowRor4>(a); }
+template <>
+__device__ __forceinline__ LamAcc<1> rot<1, kRowRor2>(const LamAcc<1>& a) { return rot1<kRowRor2>(a); }
+template <>
+__device__ __forceinline__ LamAcc<1> rot<1, kRowRor1>(const LamAcc<1>& a) { return rot1<kRowRor1>(a); }
+
+__device__ __forceinline__ LamAcc<0> readlane_acc(const LamAcc<0>& a, int lane) {
+  LamAcc<0> r;
+  r.s = readlane_f64(a.s, lane);
+  return r;
+}
+__device__ __forceinline__ LamAcc<1> readlane_acc(const LamAcc<1>& a, int lane) {
+  LamAcc<1> r;
+  r.s = readlane_f32(a.s, lane);
+  r.c = readlane_f32(a.c, lane);
+  return r;
+}
+
+// Sum over the 64 lanes of a wave; the result is uniform across the wave.
 template <int LS>
 __device__ __forceinline__ LamAcc<LS> wave_allreduce(LamAcc<LS> a) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) a.combine(a.shfl_xor(off));
-  return a.shfl(0);
+  a.combine(rot<LS, kRowRor8>(a));
+  a.combine(rot<LS, kRowRor4>(a));
+  a.combine(rot<LS, kRowRor2>(a));
+  a.combine(rot<LS, kRowRor1>(a));
+  LamAcc<LS> r = readlane_acc(a, 0);
+  r.combine(readlane_acc(a, 16));
+  r.combine(readlane_acc(a, 32));
+  r.combine(readlane_acc(a, 48));
+  return r;
+}
+
+// Double sum over the 64 lanes of a wave, uniform across the wave.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  LamAcc<0> a;
+  a.s = v;
+  return wave_allreduce<0>(a).s;
 }
 
 // Sum of n packed accumulators p[0..n), computed identically by every wave.
@@ -169,6 +252,16 @@ __device__ __forceinline__ LamAcc<LS> wave_sum_packed(const uint64_t* p, int n) 
   LamAcc<LS> a;
   for (int k = lane; k < n; k += 64) a.combine(LamAcc<LS>::unpack(p[k]));
   return wave_allreduce<LS>(a);
+}
+
+// Sum of the NW per-wave slots of a workgroup, read by every lane in slot
+// order (a uniform LDS broadcast; no cross-lane traffic).
+template <int LS, int NW>
+__device__ __forceinline__ LamAcc<LS> slots_sum(const uint64_t* slots) {
+  LamAcc<LS> a = LamAcc<LS>::unpack(slots[0]);
+#pragma unroll
+  for (int w = 1; w < NW; ++w) a.combine(LamAcc<LS>::unpack(slots[w]));
+  return a;
 }
 
 }  // namespace rcscm

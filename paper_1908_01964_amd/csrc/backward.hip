@@ -34,7 +34,7 @@ __device__ __forceinline__ double block_sum(double v, uint64_t (*red)[NT / 64], 
   const int t = threadIdx.x;
   if ((t & 63) == 0) red[phase & 1][t >> 6] = a.pack();
   __syncthreads();
-  const double s = wave_sum_packed<0>(red[phase & 1], NT / 64).s;
+  const double s = slots_sum<0, NT / 64>(red[phase & 1]).s;
   ++phase;
   return s;
 }
@@ -222,41 +222,25 @@ __global__ __launch_bounds__(NT) void backward_kernel(
     const double tr = (double)Tbr[q] - 2.0 * (double)T.x * nb * inv_taad;
     const double ti = (double)Tbi[q] - 2.0 * (double)T.y * nb * inv_taad;
     const float2* xp = x + ri.x_off + (long long)j * M;
-    double xr[MAXM], xi[MAXM], zr[MAXM], zi[MAXM];
+    double xr[MAXM], xi[MAXM];
 #pragma unroll
     for (int m = 0; m < MAXM; ++m) {
       const float2 v = (m < M) ? xp[m] : make_float2(0.f, 0.f);
       xr[m] = v.x;
       xi[m] = v.y;
     }
-#pragma unroll
-    for (int p = 0; p < MAXM; ++p) {  // z = G x
-      double ar = 0.0, ai = 0.0;
-      if (p < M) {
-#pragma unroll
-        for (int n = 0; n < MAXM; ++n) {
-          if (n < M) {
-            const double2 G = Dc->G[p * MAXM + n];
-            ar = fma(G.x, xr[n], fma(-G.y, xi[n], ar));
-            ai = fma(G.x, xi[n], fma(G.y, xr[n], ai));
-          }
-        }
-      }
-      zr[p] = ar;
-      zi[p] = ai;
-    }
     float2* gp = grad_x + ri.x_off + (long long)j * M;
 #pragma unroll
     for (int m = 0; m < MAXM; ++m) {
       if (m >= M) continue;
-      // ((R')^+ x)_m = sum_p conj(G[p][m]) z_p
+      // ((R')^+ x)_m = sum_n Q[m][n] x_n
       double yr = 0.0, yi = 0.0;
 #pragma unroll
-      for (int p = 0; p < MAXM; ++p) {
-        if (p < M) {
-          const double2 G = Dc->G[p * MAXM + m];
-          yr = fma(G.x, zr[p], fma(G.y, zi[p], yr));
-          yi = fma(G.x, zi[p], fma(-G.y, zr[p], yi));
+      for (int n = 0; n < MAXM; ++n) {
+        if (n < M) {
+          const double2 Qmn = Dc->Q[m * MAXM + n];
+          yr = fma(Qmn.x, xr[n], fma(-Qmn.y, xi[n], yr));
+          yi = fma(Qmn.x, xi[n], fma(Qmn.y, xr[n], yi));
         }
       }
       const double2 c = Dc->c[m];

@@ -77,7 +77,7 @@ struct rcscm_ctx {
   unsigned* d_status = nullptr;
   double* d_objpart = nullptr;
   float* d_uhat = nullptr;
-  float2* d_rinv = nullptr;
+  unsigned* d_chunk_status = nullptr;
   const float2* x_borrowed = nullptr;
   // checkpoints of the last iterate() call
   float* d_ck_rh = nullptr;
@@ -369,12 +369,12 @@ static rcscm_status alloc_workspace(rcscm_ctx* c) {
   RCSCM_TRY(c->alloc(&c->d_part[0], c->nchunks, "partial sums"));
   RCSCM_TRY(c->alloc(&c->d_part[1], c->nchunks, "partial sums"));
   RCSCM_TRY(c->alloc(&c->d_status, c->nrows, "status"));
+  RCSCM_TRY(c->alloc(&c->d_chunk_status, c->nchunks, "chunk status"));
   RCSCM_TRY(c->alloc(&c->d_objpart, c->nchunks, "objective partials"));
   if (c->p.rule == RCSCM_RULE_NAIVE) {
     long long maxMM = 0;
     for (int u = 0; u < c->U; ++u) maxMM = c->M[u] * c->M[u] > maxMM ? c->M[u] * c->M[u] : maxMM;
     RCSCM_TRY(c->alloc(&c->d_uhat, (size_t)(maxMM * c->nbins), "packed U^"));
-    RCSCM_TRY(c->alloc(&c->d_rinv, (size_t)c->nrows * MAXM * MAXM, "R^{-1}"));
   }
   return RCSCM_OK;
 }
@@ -401,7 +401,7 @@ size_t rcscm_workspace_bytes(int U, int I, const int* J, const int* M,
                2 * sizeof(float) + sizeof(unsigned) + sizeof(int));
   b += chunks * (2 * sizeof(ChunkInfo) + 2 * sizeof(uint64_t) + sizeof(double));
   b += bins * (sizeof(float4) + 3 * sizeof(float));
-  if (p.rule == RCSCM_RULE_NAIVE) b += bins * maxMM * sizeof(float) + rows * 64 * sizeof(float2);
+  if (p.rule == RCSCM_RULE_NAIVE) b += bins * maxMM * sizeof(float) + 0;
   return b;
 }
 
@@ -456,22 +456,36 @@ rcscm_status rcscm_init(rcscm_ctx* c, const void* x, const void* a, const void* 
   if (!c) return RCSCM_EINVAL;
   if (!x || !a || !Rp || !b) return c->fail(RCSCM_EINVAL, "x, a, Rp and b must not be NULL");
   hipStream_t s = c->stream;
-  RCSCM_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(unsigned) * c->nrows, s));
   c->lam_cur = 0;
-  launch_setup(s, c->nrows, c->d_rows, static_cast<const double2*>(a),
-               static_cast<const double2*>(Rp), static_cast<const double2*>(b), c->d_rcd,
-               c->d_rcf, c->d_rsf, c->d_status);
-  RCSCM_HIP(c, hipGetLastError());
+  InitArgs A;
+  A.rows = c->d_rows;
+  A.x = static_cast<const float2*>(x);
+  A.a = static_cast<const double2*>(a);
+  A.Rp = static_cast<const double2*>(Rp);
+  A.b = static_cast<const double2*>(b);
+  A.rh0 = rh0;
+  A.ru0 = ru0;
+  A.lam0 = lam0;
+  A.rh_c = c->p.rh0;
+  A.ru_c = c->p.ru0;
+  A.lam_c = c->p.lam0;
+  A.rcd = c->d_rcd;
+  A.rcf = c->d_rcf;
+  A.rsf = c->d_rsf;
+  A.tsig = c->d_tsig;
+  A.nu = c->d_nu;
+  A.rh = c->d_rh;
+  A.ru = c->d_ru;
+  A.lam = c->d_lam[c->lam_cur];
+  A.status = c->d_status;
+  A.chunk_status = c->d_chunk_status;
   for (int m = 2; m <= RCSCM_MAX_M; ++m) {
     const auto rg = c->m_range[m];
     if (rg.second == 0) continue;
-    launch_precompute(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rcd,
-                      static_cast<const float2*>(x), c->d_tsig, c->d_nu, c->d_status);
+    A.chunks = c->d_chunks_m + rg.first;
+    launch_init(s, m, rg.second, A);
     RCSCM_HIP(c, hipGetLastError());
   }
-  launch_fill_state(s, c->nrows, c->d_rows, rh0, ru0, lam0, c->p.rh0, c->p.ru0, c->p.lam0,
-                    c->d_rh, c->d_ru, c->d_lam[c->lam_cur], c->d_status);
-  RCSCM_HIP(c, hipGetLastError());
   c->x_borrowed = static_cast<const float2*>(x);
   c->inited = true;
   c->ck_K = -1;
@@ -515,14 +529,12 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
                        c->d_part[0], alpha, beta, c->d_status);
         RCSCM_HIP(c, hipGetLastError());
       }
-      launch_naive_rinv(s, c->nrows, c->d_rows, c->d_rcd, c->d_part[0], c->d_lam[c->lam_cur],
-                        c->d_rinv, c->d_status);
-      RCSCM_HIP(c, hipGetLastError());
       for (int m = 2; m <= RCSCM_MAX_M; ++m) {
         const auto rg = c->m_range[m];
         if (rg.second == 0) continue;
-        launch_naive_b(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rinv, c->d_ru,
-                       c->d_uhat, c->nbins, c->d_status);
+        launch_naive_b(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rcd,
+                       c->d_part[0], c->d_lam[c->lam_cur], c->d_ru, c->d_uhat, c->nbins,
+                       c->d_status);
         RCSCM_HIP(c, hipGetLastError());
       }
     }
@@ -611,9 +623,12 @@ rcscm_status rcscm_sync(rcscm_ctx* c) {
   if (!c) return RCSCM_EINVAL;
   RCSCM_HIP(c, hipStreamSynchronize(c->stream));
   if (!c->inited) return RCSCM_OK;
-  std::vector<unsigned> st(c->nrows);
+  std::vector<unsigned> st(c->nrows), cst(c->nchunks);
   RCSCM_HIP(c, hipMemcpy(st.data(), c->d_status, sizeof(unsigned) * c->nrows,
                          hipMemcpyDeviceToHost));
+  RCSCM_HIP(c, hipMemcpy(cst.data(), c->d_chunk_status, sizeof(unsigned) * c->nchunks,
+                         hipMemcpyDeviceToHost));
+  for (int k = 0; k < c->nchunks; ++k) st[c->h_chunks[k].row] |= cst[k];
   const unsigned order[] = {ST_NONFINITE_IN, ST_NOT_NULL, ST_NOT_PSD, ST_NONFINITE_STATE,
                             ST_LAM_NONPOS};
   for (unsigned bit : order) {

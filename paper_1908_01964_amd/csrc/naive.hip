@@ -1,6 +1,6 @@
 // Naive EM update (Sec. II-B-2, eqs. (13)-(20)) on gfx950: the comparator.
 //
-// One iteration is three launches:
+// One iteration is two launches per microphone count:
 //   naive_a   (per chunk of bins)  E-step with one M x M factorisation per bin
 //             and the r^h update:
 //               R~    = R' + lambda~ b b^H                          eq. (13)
@@ -12,12 +12,12 @@
 //             U^ is stored packed (M real diagonal entries, then the
 //             upper triangle) and the chunk's sum of b^H U^ b / r~u is
 //             written as a partial sum for eq. (18).
-//   naive_rinv (per row)  lambda = mean of the partial sums (eq. (18)),
-//             R = R' + lambda b b^H (eq. (19)) and R^{-1} by an FP64
-//             Cholesky factorisation.
-//   naive_b   (per chunk)  r^u = tr(R^{-1} U^) / M                      eq. (20)
+//   naive_b   (per chunk)  lambda = mean of the partial sums (eq. (18)),
+//             R = R' + lambda b b^H (eq. (19)) and R^{-1} by FP64
+//             Gauss-Jordan elimination, then r^u = tr(R^{-1} U^) / M    eq. (20)
 // No step uses the pseudoinverse of R' or the Sherman-Morrison identity.
 #include "accel_common.h"
+#include "small_linalg.h"
 
 namespace rcscm {
 
@@ -187,99 +187,43 @@ __global__ __launch_bounds__(kNT) void naive_a_kernel(
   if (bad) atomicOr(status + ck.row, ST_NONFINITE_STATE);
 }
 
-__device__ inline double2 dmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// lambda from the partial sums, then R^{-1} = (R' + lambda b b^H)^{-1} in FP64.
-__global__ __launch_bounds__(64) void naive_rinv_kernel(const RowInfo* __restrict__ rows,
-                                                        const RowConstD* __restrict__ rcd,
-                                                        const uint64_t* __restrict__ part,
-                                                        float* __restrict__ lam,
-                                                        float2* __restrict__ rinv,
-                                                        unsigned* __restrict__ status) {
-  const int r = blockIdx.x;
-  const int t = threadIdx.x;
-  const RowInfo ri = rows[r];
-  const int M = ri.M;
-  const RowConstD* D = rcd + r;
-  __shared__ double2 sA[MAXM][MAXM], sL[MAXM][MAXM], sLi[MAXM][MAXM];
-  __shared__ double sinv;
-  const float l = wave_sum_packed<0>(part + ri.part_off, ri.nparts).mean(1.0 / (double)ri.J);
-  if (t == 0) {
-    lam[r] = l;
-    if (!(l > 0.0f) || !isfinite(l)) atomicOr(status + r, ST_LAM_NONPOS);
-  }
-  const double ld = (double)l;
-  if (t < M * M) {
-    const int i = t / M, j = t % M;
-    const double2 bi = D->b[i], bj = D->b[j];
-    const double2 bb = dmul(bi, make_double2(bj.x, -bj.y));
-    const double2 rp = D->Rp[i * MAXM + j];
-    sA[i][j] = make_double2(rp.x + ld * bb.x, rp.y + ld * bb.y);
-    sL[i][j] = make_double2(0.0, 0.0);
-    sLi[i][j] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int k = 0; k < M; ++k) {
-    if (t == 0) {
-      const double d = fmax(sA[k][k].x, 1e-300);
-      const double lk = sqrt(d);
-      sL[k][k] = make_double2(lk, 0.0);
-      sinv = 1.0 / lk;
-    }
-    __syncthreads();
-    if (t > k && t < M) sL[t][k] = make_double2(sA[t][k].x * sinv, sA[t][k].y * sinv);
-    __syncthreads();
-    if (t < M * M) {
-      const int i = t / M, j = t % M;
-      if (j > k && i >= j) {
-        const double2 p = dmul(sL[i][k], make_double2(sL[j][k].x, -sL[j][k].y));
-        sA[i][j].x -= p.x;
-        sA[i][j].y -= p.y;
-      }
-    }
-    __syncthreads();
-  }
-  if (t < M) {  // column t of L^{-1}
-    const int j = t;
-    for (int i = j; i < M; ++i) {
-      double2 s = make_double2(i == j ? 1.0 : 0.0, 0.0);
-      for (int k = j; k < i; ++k) {
-        const double2 p = dmul(sL[i][k], sLi[k][j]);
-        s.x -= p.x;
-        s.y -= p.y;
-      }
-      const double inv = 1.0 / sL[i][i].x;
-      sLi[i][j] = make_double2(s.x * inv, s.y * inv);
-    }
-  }
-  __syncthreads();
-  if (t < M * M) {  // R^{-1} = L^{-H} L^{-1}: (i, j) = sum_k conj(Li[k][i]) Li[k][j]
-    const int i = t / M, j = t % M;
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = 0; k < M; ++k) {
-      const double2 p = dmul(make_double2(sLi[k][i].x, -sLi[k][i].y), sLi[k][j]);
-      s.x += p.x;
-      s.y += p.y;
-    }
-    rinv[(long long)r * (MAXM * MAXM) + i * MAXM + j] = make_float2((float)s.x, (float)s.y);
-  }
-}
-
+// lambda = mean of the partial sums (eq. (18)), R^{-1} = (R' + lambda b b^H)^{-1}
+// (eq. (19)) by FP64 Gauss-Jordan in LDS (every workgroup of the row does it;
+// the first one stores lambda), then r^u = tr(R^{-1} U^) / M per bin (eq. (20)).
 template <int M>
 __global__ __launch_bounds__(kNT) void naive_b_kernel(const ChunkInfo* __restrict__ chunks,
                                                       const RowInfo* __restrict__ rows,
-                                                      const float2* __restrict__ rinv,
+                                                      const RowConstD* __restrict__ rcd,
+                                                      const uint64_t* __restrict__ part,
+                                                      float* __restrict__ lam,
                                                       float* __restrict__ ru,
                                                       const float* __restrict__ uhat,
                                                       long long nbins,
                                                       unsigned* __restrict__ status) {
   const ChunkInfo ck = chunks[blockIdx.x];
   const RowInfo ri = rows[ck.row];
+  const RowConstD* D = rcd + ck.row;
   const int t = threadIdx.x;
+  const int i = t / M, j = t % M;
+  __shared__ double2 aug[M][2 * M];
   __shared__ float2 sR[M * M];
-  if (t < M * M) sR[t] = rinv[(long long)ck.row * (MAXM * MAXM) + (t / M) * MAXM + (t % M)];
+  const float l = wave_sum_packed<0>(part + ri.part_off, ri.nparts).mean(1.0 / (double)ri.J);
+  if (ck.start == 0 && t == 0) {
+    lam[ck.row] = l;
+    if (!(l > 0.0f) || !isfinite(l)) atomicOr(status + ck.row, ST_LAM_NONPOS);
+  }
+  if (t < 64) {  // R^{-1} by wave 0
+    if (t < M * M) {
+      const double2 bb = zmul(D->b[i], zconj(D->b[j]));
+      const double2 rp = D->Rp[i * MAXM + j];
+      aug[i][j] = make_double2(rp.x + (double)l * bb.x, rp.y + (double)l * bb.y);
+      aug[i][M + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    wave_sync();
+    double det;
+    gj_inverse_hpd_wave<M>(aug, 0.0, &det);
+    if (t < M * M) sR[t] = make_float2((float)aug[i][M + j].x, (float)aug[i][M + j].y);
+  }
   __syncthreads();
   bool bad = false;
   for (int jj = t; jj < ck.len; jj += kNT) {
@@ -333,21 +277,14 @@ void launch_naive_a(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
 #undef RCSCM_NA
 }
 
-void launch_naive_rinv(hipStream_t s, int nrows, const RowInfo* rows, const RowConstD* rcd,
-                       const uint64_t* part, float* lam, float2* rinv, unsigned* status) {
-  if (nrows <= 0) return;
-  hipLaunchKernelGGL(naive_rinv_kernel, dim3(nrows), dim3(64), 0, s, rows, rcd, part, lam, rinv,
-                     status);
-}
-
 void launch_naive_b(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
-                    const RowInfo* rows, const float2* rinv, float* ru, const float* uhat,
-                    long long nbins, unsigned* status) {
+                    const RowInfo* rows, const RowConstD* rcd, const uint64_t* part, float* lam,
+                    float* ru, const float* uhat, long long nbins, unsigned* status) {
   if (nchunks <= 0) return;
-#define RCSCM_NB(MM)                                                                          \
-  case MM:                                                                                    \
-    hipLaunchKernelGGL(naive_b_kernel<MM>, dim3(nchunks), dim3(kNT), 0, s, chunks, rows, rinv, \
-                       ru, uhat, nbins, status);                                              \
+#define RCSCM_NB(MM)                                                                           \
+  case MM:                                                                                     \
+    hipLaunchKernelGGL(naive_b_kernel<MM>, dim3(nchunks), dim3(kNT), 0, s, chunks, rows, rcd, \
+                       part, lam, ru, uhat, nbins, status);                                    \
     break;
   switch (M) {
     RCSCM_NB(2)

@@ -39,9 +39,8 @@ struct RowConstF {
 
 // FP64 per-row setup results (precompute, objective, adjoint).
 struct RowConstD {
-  double2 G[MAXM * MAXM];  // F^H with F F^H = (R')^+, row-major (z = G x)
+  double2 Q[MAXM * MAXM];  // (R')^+, Hermitian, row-major
   double2 c[MAXM];         // (R')^+ a
-  double2 g[MAXM];         // F^H a  (|g|^2 = tau^(aa))
   double2 b[MAXM];         // unit null vector of R'
   double2 a[MAXM];         // steering vector
   double2 Rp[MAXM * MAXM]; // projected, Hermitised R' (R' b = 0), row-major
@@ -68,17 +67,33 @@ enum : unsigned {
 };
 
 // Kernel launchers (defined in the .hip files).
-void launch_setup(hipStream_t s, int nrows, const RowInfo* rows, const double2* a,
-                  const double2* Rp, const double2* b, RowConstD* rcd, RowConstF* rcf,
-                  RowSpatialF* rsf, unsigned* status);
 
-void launch_precompute(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
-                       const RowInfo* rows, const RowConstD* rcd, const float2* x,
-                       float4* tsig, float* nu, unsigned* status);
-
-void launch_fill_state(hipStream_t s, int nrows, const RowInfo* rows, const float* rh0,
-                       const float* ru0, const float* lam0, float rh_c, float ru_c, float lam_c,
-                       float* rh, float* ru, float* lam, unsigned* status);
+// Per-row FP64 setup + per-bin precompute + initial state, one launch per
+// microphone count M over the chunks of that M.  Writes status[row] (setup
+// bits, by the row's first chunk) and chunk_status[chunk] (per-chunk bits).
+struct InitArgs {
+  const ChunkInfo* chunks;
+  const RowInfo* rows;
+  const float2* x;
+  const double2* a;
+  const double2* Rp;
+  const double2* b;
+  const float* rh0;  // may be null: rh_c
+  const float* ru0;  // may be null: ru_c
+  const float* lam0; // may be null: lam_c
+  float rh_c, ru_c, lam_c;
+  RowConstD* rcd;
+  RowConstF* rcf;
+  RowSpatialF* rsf;
+  float4* tsig;
+  float* nu;
+  float* rh;
+  float* ru;
+  float* lam;
+  unsigned* status;
+  unsigned* chunk_status;
+};
+void launch_init(hipStream_t s, int M, int nchunks, const InitArgs& args);
 
 // RESIDENT schedule: rows in row_list (all with J <= nt * bpl).
 bool resident_supported(int nt, int bpl);
@@ -112,11 +127,9 @@ void launch_naive_a(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
                     const RowInfo* rows, const RowSpatialF* rsf, const float2* x, float* rh,
                     const float* ru, const float* lam, float* uhat, long long nbins,
                     uint64_t* part, float alpha, float beta, unsigned* status);
-void launch_naive_rinv(hipStream_t s, int nrows, const RowInfo* rows, const RowConstD* rcd,
-                       const uint64_t* part, float* lam, float2* rinv, unsigned* status);
 void launch_naive_b(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
-                    const RowInfo* rows, const float2* rinv, float* ru, const float* uhat,
-                    long long nbins, unsigned* status);
+                    const RowInfo* rows, const RowConstD* rcd, const uint64_t* part, float* lam,
+                    float* ru, const float* uhat, long long nbins, unsigned* status);
 
 // Adjoint of the RESIDENT/STREAM accelerated forward (checkpointed).
 void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_list,

@@ -1,0 +1,75 @@
+// Small dense FP64 linear algebra done by the 64 lanes of ONE wave of a
+// workgroup (matrices of order M <= 8 held in LDS).  Only wave 0 calls these
+// functions; lanes synchronise with wave_sync() (the wave executes in
+// lock-step, so a wave-scope fence on the LDS traffic is all that is needed).
+// The caller follows with __syncthreads() before other waves read results.
+#pragma once
+
+#include "rcscm_internal.h"
+
+namespace rcscm {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zmulc(double2 a, double2 b) {  // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ bool zfinite(double2 v) { return isfinite(v.x) && isfinite(v.y); }
+
+// In-place inverse of a Hermitian positive-definite M x M matrix by
+// Gauss-Jordan elimination without pivoting (stable for HPD matrices: every
+// pivot is a positive Schur-complement diagonal).  aug is LDS [M][2M]:
+// [A | I] on entry, [I | A^{-1}] on exit.  Lane t < M*M of wave 0 updates
+// entry (t / M, t % M) of both halves in each of the M elimination steps.
+// Returns false (and continues with a clamped pivot) when a pivot is <= tol;
+// *pivprod receives the product of the pivots (= det A).
+template <int M>
+__device__ bool gj_inverse_hpd_wave(double2 (*aug)[2 * M], double tol, double* pivprod) {
+  const int t = threadIdx.x;
+  const int i = t / M, j = t % M;
+  const bool on = t < M * M;
+  bool ok = true;
+  double prod = 1.0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double p = aug[k][k].x;
+    if (!(p > tol)) {
+      ok = false;
+      p = fmax(tol, 1e-300);
+    }
+    prod *= p;
+    const double ip = 1.0 / p;
+    double2 f = make_double2(0.0, 0.0), r1 = f, r2 = f;
+    if (on) {
+      f = aug[i][k];
+      r1 = aug[k][j];
+      r2 = aug[k][M + j];
+    }
+    wave_sync();
+    if (on) {
+      const double2 n1 = make_double2(r1.x * ip, r1.y * ip);
+      const double2 n2 = make_double2(r2.x * ip, r2.y * ip);
+      if (i == k) {
+        aug[k][j] = n1;
+        aug[k][M + j] = n2;
+      } else {
+        const double2 d1 = zmul(f, n1), d2 = zmul(f, n2);
+        aug[i][j] = make_double2(aug[i][j].x - d1.x, aug[i][j].y - d1.y);
+        aug[i][M + j] = make_double2(aug[i][M + j].x - d2.x, aug[i][M + j].y - d2.y);
+      }
+    }
+    wave_sync();
+  }
+  *pivprod = prod;
+  return ok;
+}
+
+}  // namespace rcscm
