@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--naive-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=0, help="0 = enough runs for >= 10 s of CPU work")
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the estimation is independent per frequency row and "
@@ -224,6 +226,15 @@ def main():
     inputs = to_device(probs)
     del probs
     dev = inputs[0].device
+    if args.copy_calibration_mb > 0:
+        # a plain device copy of known size, so hardware byte counters of the kernels can be
+        # scaled by what the same counters read for this copy (rocprofv3 --pmc runs)
+        n = int(args.copy_calibration_mb * (1 << 20)) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tuned = best_params(I, Js, Ms, K) if (args.schedule == "auto" and args.block < 0) else {}
     sched = dict(schedule=args.schedule if args.schedule != "auto" else tuned.get("schedule", "auto"),
                  block=args.block if args.block >= 0 else tuned.get("block", 0),
@@ -250,6 +261,15 @@ def main():
         ctxn.close()
         naive = {"value": updates * args.naive_steps / wall_n,
                  "ms_per_step": wall_n / args.naive_steps * 1e3, "phases_us": phases_n}
+    first = None
+    if args.naive_steps > 0 and max(Js) <= 4096:
+        # the paper's first-stage rule (Algorithm 1) on the same step, for the three-way comparison
+        ctxf = Context(I, Js, Ms, rule="first")
+        wall_f, phases_f = time_steps(ctxf, inputs, dict(out), K, args.naive_steps, 1, torch)
+        ctxf.sync()
+        ctxf.close()
+        first = {"value": updates * args.naive_steps / wall_f,
+                 "ms_per_step": wall_f / args.naive_steps * 1e3, "phases_us": phases_f}
 
     # roofline of the dominant kernel
     it_us = phases["iterate"]
@@ -286,6 +306,9 @@ def main():
         line["naive"] = naive
         line["speedup_vs_naive"] = value / naive["value"]
         line["iterate_speedup_vs_naive"] = naive["phases_us"]["iterate"] / phases["iterate"]
+    if first is not None:
+        line["first_stage"] = first
+        line["iterate_speedup_vs_first_stage"] = first["phases_us"]["iterate"] / phases["iterate"]
     if cb is not None:
         line["cpu_baseline"] = cb
         errs = {}

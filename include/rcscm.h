@@ -10,19 +10,23 @@
  * estimates theta = {r^h_ij, r^u_ij, lambda_i} by the MAP-EM iteration of
  * Sec. II-B-2 and extracts the target with the multichannel Wiener filter.
  *
- * Two update rules are provided:
+ * Three update rules are provided (identical iterates in exact arithmetic):
  *   RCSCM_RULE_ACCEL - the second-stage accelerated rule (Algorithm 2,
  *                      eqs. (46)-(56)): scalar work per bin, one reduction
  *                      over frames per frequency for lambda_i.
  *   RCSCM_RULE_NAIVE - the literal E-step/M-step (eqs. (13)-(20)) with an
  *                      M x M factorisation of the model covariance per bin.
+ *   RCSCM_RULE_FIRST - the first-stage accelerated rule (Algorithm 1,
+ *                      eqs. (27)-(45)): two M x M inverses per frequency and
+ *                      O(M^2) quadratic forms per bin per iteration; needs
+ *                      J_u <= 4096.
  *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers owned by the caller, unless stated
  *     otherwise.  Complex arrays are interleaved (re, im).
  *   - Work is enqueued on the stream given at create (a hipStream_t passed as
  *     void*; NULL = the legacy default stream).  Only rcscm_sync,
- *     rcscm_objective and rcscm_last_status block the host.
+ *     rcscm_objective and rcscm_destroy block the host.
  *   - Errors are returned as rcscm_status; nothing throws across the ABI.
  *     Argument errors are detected on the host before any device work.
  *     Data errors found by kernels (non-null b, non-PSD R', non-finite x or
@@ -66,7 +70,7 @@ typedef enum {
   RCSCM_ESTATE = -8      /* call out of order (e.g. iterate before init)         */
 } rcscm_status;
 
-typedef enum { RCSCM_RULE_NAIVE = 0, RCSCM_RULE_ACCEL = 1 } rcscm_rule;
+typedef enum { RCSCM_RULE_NAIVE = 0, RCSCM_RULE_ACCEL = 1, RCSCM_RULE_FIRST = 2 } rcscm_rule;
 
 /* How the K-iteration loop of the accelerated rule is executed.
  *   STREAM:   one pass over HBM per iteration (K+1 launches, the lambda
@@ -74,7 +78,8 @@ typedef enum { RCSCM_RULE_NAIVE = 0, RCSCM_RULE_ACCEL = 1 } rcscm_rule;
  *             split into fixed-size chunks.  Works for any J.
  *   RESIDENT: one workgroup owns a frequency row for all K iterations and
  *             keeps its per-bin data in registers (one launch per
- *             bins-per-lane class).  Needs J_u <= 16384.
+ *             (workgroup size, bins-per-lane) class).  Needs J_u <= 8192
+ *             (J_u <= 16 * block for an explicit block below 1024).
  *   AUTO:     RESIDENT when every row fits, else STREAM.                  */
 typedef enum { RCSCM_SCHED_AUTO = 0, RCSCM_SCHED_STREAM = 1, RCSCM_SCHED_RESIDENT = 2 } rcscm_sched;
 
@@ -95,10 +100,11 @@ typedef struct {
   int rule;        /* rcscm_rule; default RCSCM_RULE_ACCEL                           */
   int schedule;    /* rcscm_sched; default RCSCM_SCHED_AUTO                          */
   int lamsum;      /* rcscm_lamsum; default RCSCM_LAMSUM_F64                         */
-  int block;       /* threads per workgroup of the RESIDENT kernel: 0 (auto), 64,
-                      128, 256, 512 or 1024                                          */
-  int chunk;       /* bins per workgroup of the STREAM kernel: 0 (auto) or a
-                      multiple of 256 in [256, 8192]                                  */
+  int block;       /* threads per workgroup of the RESIDENT kernel: 0 (per row: the
+                      smallest of 64..1024 holding the row at <= 4 bins per lane),
+                      64, 128, 256, 512 or 1024                                      */
+  int chunk;       /* bins per workgroup of the STREAM, init, extract and naive
+                      kernels: 0 (1024), 256, 512, 1024 or 2048                      */
   unsigned flags;  /* RCSCM_FLAG_* */
 } rcscm_params;
 
@@ -122,23 +128,25 @@ rcscm_status rcscm_create_batch(rcscm_ctx** out, int U, int I, const int* J, con
 /* Per-frequency setup and per-bin precomputation (Algorithm 2, before the
  * loop; eqs. (32), (33), (46)-(48) and the pseudoinverse of eq. (26)):
  *   - b is normalised and R' projected onto the orthogonal complement of b,
- *     in FP64; (R')^+ = (R' + b b^H)^{-1} - b b^H from an FP64 Cholesky
- *     factor C C^H = R' + b b^H;
+ *     in FP64; (R')^+ = (R' + s b b^H)^{-1} - b b^H / s with s = tr(R')/(M-1),
+ *     the inverse by FP64 Gauss-Jordan elimination;
  *   - per bin, in FP64 from the complex64 x, then stored as float:
  *     tau^(ax) = a^H (R')^+ x, sigma^(bx) = b^H x and
- *     nu = tau^(xx) - |tau^(ax)|^2 / tau^(aa) >= 0 (as a sum of squares).
+ *     nu = tau^(xx) - |tau^(ax)|^2 / tau^(aa) >= 0;
+ *   - the initial state from rh0/ru0/lam0.
+ * One launch per microphone count.
  * x: complex64 batch layout; a, Rp, b: complex128 batch layout.
  * rh0, ru0: float batch layout [..][I][J_u] or NULL (use params->rh0/ru0);
  * lam0: float [U][I] or NULL (params->lam0).  All are read during this call's
  * stream work only; the ACCEL rule keeps no reference to x afterwards.  The
- * NAIVE rule re-reads x in every iteration: x must stay valid and unchanged
- * until the context is destroyed.  Data errors (ENOTNULL, ENOTPSD, ENONFINITE)
+ * NAIVE and FIRST rules re-read x in every iteration: x must stay valid and
+ * unchanged until the context is destroyed.  Data errors (ENOTNULL, ENOTPSD, ENONFINITE)
  * surface at the next rcscm_sync. */
 rcscm_status rcscm_init(rcscm_ctx* ctx, const void* x, const void* a, const void* Rp,
                         const void* b, const float* rh0, const float* ru0, const float* lam0);
 
 /* Runs K >= 0 further EM iterations from the current state (eqs. (13)-(20)
- * for NAIVE; Algorithm 2 for ACCEL).  Within an iteration r^h and lambda use
+ * for NAIVE; Algorithm 1 for FIRST; Algorithm 2 for ACCEL).  Within an iteration r^h and lambda use
  * the values at its start; r^u uses the new lambda.  iterate(K1) followed by
  * iterate(K2) gives the same state as iterate(K1+K2) for a fixed schedule.
  * Asynchronous.  Errors: ESTATE before init, ESHAPE for K < 0. */

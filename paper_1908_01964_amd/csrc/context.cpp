@@ -58,6 +58,7 @@ struct rcscm_ctx {
     int nt, bpl, count, offset;
   };
   std::vector<ResClass> res_classes;
+  std::vector<ResClass> first_classes;  // FIRST rule: nt field holds M
 
   Buffers mem;
   RowInfo* d_rows = nullptr;
@@ -193,7 +194,7 @@ static rcscm_status validate(int U, int I, const int* J, const int* M, const rcs
     *msg = "scalar initial values must be finite and > 0";
     return RCSCM_EINVAL;
   }
-  if (p->rule != RCSCM_RULE_NAIVE && p->rule != RCSCM_RULE_ACCEL) {
+  if (p->rule != RCSCM_RULE_NAIVE && p->rule != RCSCM_RULE_ACCEL && p->rule != RCSCM_RULE_FIRST) {
     *msg = "unknown rule";
     return RCSCM_EINVAL;
   }
@@ -229,6 +230,10 @@ static rcscm_status validate(int U, int I, const int* J, const int* M, const rcs
       *msg = "RESIDENT schedule (or checkpoints) needs J <= 16 * block (8192 for block 1024)";
       return RCSCM_ESHAPE;
     }
+  }
+  if (p->rule == RCSCM_RULE_FIRST && maxJ > 16 * 256) {
+    *msg = "the FIRST rule needs J <= 4096";
+    return RCSCM_ESHAPE;
   }
   if ((p->flags & RCSCM_FLAG_CHECKPOINT) && p->rule != RCSCM_RULE_ACCEL) {
     *msg = "checkpoints (backward) need the ACCEL rule";
@@ -337,6 +342,19 @@ static rcscm_status build_tables(rcscm_ctx* c) {
         best_bins = bins;
         c->res_nt = rc.nt;  // reported by rcscm_get_schedule: the class with most bins
       }
+    }
+  }
+  if (c->p.rule == RCSCM_RULE_FIRST) {
+    std::map<std::pair<int, int>, std::vector<int>> cls;  // (M, bins per lane)
+    for (int r = 0; r < c->nrows; ++r) {
+      const int bpl = first_stage_bpl(c->h_rows[r].J);
+      if (bpl < 0) return c->fail(RCSCM_ESHAPE, "row too long for the FIRST rule");
+      cls[{c->h_rows[r].M, bpl}].push_back(r);
+    }
+    for (auto& kv : cls) {
+      c->first_classes.push_back(rcscm_ctx::ResClass{kv.first.first, kv.first.second,
+                                                     (int)kv.second.size(), (int)row_list.size()});
+      row_list.insert(row_list.end(), kv.second.begin(), kv.second.end());
     }
   }
   if (row_list.empty()) row_list.push_back(0);
@@ -519,6 +537,15 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
   if (K == 0) return RCSCM_OK;
   hipStream_t s = c->stream;
   const float alpha = (float)c->p.alpha, beta = (float)c->p.beta;
+  if (c->p.rule == RCSCM_RULE_FIRST) {
+    for (const auto& cl : c->first_classes) {
+      launch_first_stage(s, cl.nt, cl.bpl, cl.count, c->d_row_list + cl.offset, c->d_rows,
+                         c->d_rcf, c->d_rcd, c->x_borrowed, c->d_rh, c->d_ru,
+                         c->d_lam[c->lam_cur], alpha, beta, K, c->d_status);
+      RCSCM_HIP(c, hipGetLastError());
+    }
+    return RCSCM_OK;
+  }
   if (c->p.rule == RCSCM_RULE_NAIVE) {
     for (int k = 0; k < K; ++k) {
       for (int m = 2; m <= RCSCM_MAX_M; ++m) {

@@ -131,6 +131,14 @@ void launch_naive_b(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
                     const RowInfo* rows, const RowConstD* rcd, const uint64_t* part, float* lam,
                     float* ru, const float* uhat, long long nbins, unsigned* status);
 
+// FIRST-STAGE rule (Algorithm 1): one workgroup of 256 lanes per row, x in
+// registers; bpl = first_stage_bpl(J) in {1, 2, 4, 8, 16} (-1: row too long).
+int first_stage_bpl(int J);
+void launch_first_stage(hipStream_t s, int M, int bpl, int nrows, const int* row_list,
+                        const RowInfo* rows, const RowConstF* rcf, const RowConstD* rcd,
+                        const float2* x, float* rh, float* ru, float* lam, float alpha,
+                        float beta, int K, unsigned* status);
+
 // Adjoint of the RESIDENT/STREAM accelerated forward (checkpointed).
 void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_list,
                      const RowInfo* rows, const RowConstF* rcf, const RowConstD* rcd,

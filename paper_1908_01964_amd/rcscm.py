@@ -20,7 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "rcscm.h")
 OK, EINVAL, ESHAPE, ENOTNULL, ENOTPSD, ENONFINITE, EDEVICE, ENOMEM, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOTNULL", -4: "ENOTPSD",
                 -5: "ENONFINITE", -6: "EDEVICE", -7: "ENOMEM", -8: "ESTATE"}
-RULES = {"naive": 0, "accel": 1}
+RULES = {"naive": 0, "accel": 1, "first": 2}
 SCHEDULES = {"auto": 0, "stream": 1, "resident": 2}
 LAMSUMS = {"f64": 0, "kahan32": 1}
 FLAG_GRAPH = 1

@@ -50,6 +50,8 @@ def _create(I=4, J=16, M=4, **kw):
     (dict(J=20000, schedule="resident", block=1024), R.ESHAPE, "RESIDENT"),
     (dict(J=5000, checkpoint=True, block=256), R.ESHAPE, "RESIDENT"),
     (dict(rule="naive", checkpoint=True), R.EINVAL, "checkpoints"),
+    (dict(rule="first", J=5000), R.ESHAPE, "FIRST"),
+    (dict(rule=3), R.EINVAL, "rule"),
 ])
 def test_create_rejects_bad_arguments_on_host(kw, status, msg):
     st, err = _create(**kw)

@@ -221,3 +221,35 @@ def test_config1_full_size_naive_sampled_rows():
     e = errors(got, ref)
     print("config1 naive (sampled)", e)
     assert all(v < 1e-3 for v in e.values()), e
+
+
+def _oracle_first(p, K):
+    from oracle import accel as o_accel
+    from oracle import extract as o_extract
+    from oracle import first_stage
+    st = o_accel.init_state(p.I, p.J)
+    rh, ru, lam = first_stage.run(p.x, p.a, p.Rp, p.b, *st, K, ALPHA, BETA)
+    return dict(rh=rh, ru=ru, lam=lam, s_hat=o_extract.s_hat(p.x, p.a, p.Rp, p.b, rh, ru, lam))
+
+
+@pytest.mark.parametrize("M,J", [(2, 1), (3, 65), (4, 257), (5, 300), (6, 1001), (8, 129)])
+def test_first_stage_rule_vs_oracle(M, J):
+    p = make_problem(M, 3, J, config=440 + M, spatial="sinc" if M % 2 == 0 else "random",
+                     n_fft=8)
+    ref = _oracle_first(p, 10)
+    out = gpu_run(p, 10, rule="first")[0]
+    e = errors(out, ref)
+    print("first-stage", M, J, e)
+    assert all(v < 1e-3 for v in e.values()), e
+
+
+def test_first_stage_config1_sampled_rows():
+    """Algorithm 1 at full config 1 size; 16 sampled rows against the FP64 first-stage oracle."""
+    p = config(1)
+    out = gpu_run(p, 20, rule="first")[0]
+    sel = np.linspace(0, p.I - 1, 16).round().astype(int)
+    ref = _oracle_first(config(1, freqs=sel), 20)
+    got = {k: v[sel] for k, v in out.items()}
+    e = errors(got, ref)
+    print("config1 first-stage (sampled)", e)
+    assert all(v < 1e-3 for v in e.values()), e
