@@ -187,6 +187,38 @@ def make_problem(M: int, I: int, J: int, *, config: int = 100, utterance: int = 
     return p
 
 
+def make_bss_problem(M: int, I: int, J: int, *, config: int = 600, target: int = 0,
+                     perturb: float = 0.0, freqs: Optional[Sequence[int]] = None) -> dict:
+    """Determined mixture x_ij = A_i s_ij (eq. (1)) with one target and M-1 noise sources.
+
+    A_i ~ CN(0, I) (M x M); the demixing matrix is W_i = A_i^{-1} (I + perturb E_i)
+    with E_i ~ CN(0, I) (perturb = 0: a perfect separation).  s_target ~ CN(0, r),
+    r ~ Gamma(0.5, 1); noise sources ~ CN(0, r), r ~ Gamma(2, 0.5).
+    Returns dict(x complex64 [I, J, M], W complex128 [I, M, M], A, s complex128
+    [I, J, M], target).
+    """
+    if freqs is None:
+        freqs = np.arange(I)
+    freqs = np.asarray(freqs, dtype=np.int64)
+    n = len(freqs)
+    x = np.empty((n, J, M), np.complex64)
+    W = np.empty((n, M, M), np.complex128)
+    A_all = np.empty((n, M, M), np.complex128)
+    s_all = np.empty((n, J, M), np.complex128)
+    for r, i in enumerate(freqs):
+        rng = _rng(config, 0, int(i))
+        A = _cn(rng, (M, M))
+        E = _cn(rng, (M, M))
+        pw = np.where(np.arange(M) == target, rng.gamma(0.5, 1.0, (J, M)),
+                      rng.gamma(2.0, 0.5, (J, M)))
+        s = np.sqrt(pw) * _cn(rng, (J, M))
+        x[r] = s @ A.T
+        W[r] = np.linalg.inv(A) @ (np.eye(M) + perturb * E)
+        A_all[r] = A
+        s_all[r] = s
+    return dict(x=x, W=W, A=A_all, s=s_all, target=int(target), freqs=freqs)
+
+
 # --- the five named workloads -------------------------------------------------
 
 CONFIGS = {
