@@ -188,6 +188,27 @@ rcscm_status rcscm_objective(rcscm_ctx* ctx, double* nlp);
 rcscm_status rcscm_backward(rcscm_ctx* ctx, const void* x, const void* grad_s_hat, void* grad_x,
                             float* grad_rh0, float* grad_lam0);
 
+/* Builds the inputs of rcscm_init from a determined separation, as the paper
+ * obtains them from ILRMA (Sec. II-B-1 eq. (11); Sec. II-B-3 eqs. (22), (23)):
+ *   W       complex128 [..][I][M_u][M_u] demixing matrices, row m = w_m^H
+ *           (separated signals y = W x); read only;
+ *   target  HOST int[U]: index n_h of the target source per utterance;
+ *   a       out complex128 [..][I][M_u]: a_i = column n_h of W^{-1};
+ *   Rp      out complex128 [..][I][M_u][M_u]: R'_i = (1/J) sum_j W^{-1}
+ *           diag(|w_m^H x|^2 with the n_h-th entry 0) W^{-H}   (eq. (11));
+ *   b       out complex128 [..][I][M_u]: w_{n_h} / |w_{n_h}|, the unit null
+ *           vector of R';
+ *   ru0     out float [..][I][J_u] or NULL: (1/M) y^(u)H (R')^+ y^(u) with the
+ *           back-projected noise image y^(u) of eq. (23)        (eq. (22));
+ *   lam0    out float [U][I] or NULL: the minimum nonzero eigenvalue of R'.
+ * x as in rcscm_init.  All arithmetic is FP64 on the device.  Asynchronous
+ * (after a small host-to-device copy of the target indices).  Errors: EINVAL
+ * (NULL pointers, target out of range); a singular W is reported as ENOTPSD
+ * by the next rcscm_sync.  The initialisation of r^h from the NMF factors of
+ * ILRMA (eq. (21)) is the caller's (pass it to rcscm_init as rh0). */
+rcscm_status rcscm_backproject(rcscm_ctx* ctx, const void* x, const void* W, const int* target,
+                               void* a, void* Rp, void* b, float* ru0, float* lam0);
+
 /* Frees every device buffer of the context (after waiting for its stream). */
 void rcscm_destroy(rcscm_ctx* ctx);
 

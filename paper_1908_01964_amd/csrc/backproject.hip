@@ -1,0 +1,333 @@
+// Rank-(M-1) SCM of the diffuse noise from a demixing matrix, and the
+// paper's initialisation of r^u and lambda (Sec. II-B-1 eq. (11); Sec. II-B-3
+// eqs. (22), (23)), in FP64.
+//
+// With W_i = (w_1 ... w_M)^H, y_ij = W_i x_ij and A_i = W_i^{-1} = (a_1 ... a_M):
+//   eq. (11)  R'_i = (1/J) sum_j A diag(|y_1|^2, .., 0 at n_h, .., |y_M|^2) A^H
+//                  = sum_{m != n_h} p_m a_m a_m^H,   p_m = (1/J) sum_j |y_m,ij|^2
+//   b_i = w_{n_h} / |w_{n_h}|   (W A = I, so R' w_{n_h} = 0: the null vector)
+//   a_i = a_{n_h}               (the target's steering vector)
+//   eqs. (22)-(23): y^(u) = A (y with the n_h-th entry zeroed) lies in
+//   range(R') = span{a_m, m != n_h}; for R' = B P B^H with B of full column
+//   rank, (R')^+ = B^{+H} P^{-1} B^+, hence
+//   r^u_0 = (1/M) y^(u)H (R')^+ y^(u) = (1/M) sum_{m != n_h} |y_m|^2 / p_m
+//   lambda_0 = min nonzero eigenvalue of R' = min eigenvalue of the
+//   (M-1) x (M-1) Gram matrix P^{1/2} B^H B P^{1/2} (cyclic complex Jacobi).
+// Launches: bp_power (per chunk: partial sums of |y_m|^2), bp_row (per row:
+// A = W^{-1} by Gauss-Jordan with partial pivoting, a, R', b, lambda_0),
+// bp_ru (per chunk: r^u_0).
+#include "accel_common.h"
+#include "small_linalg.h"
+
+namespace rcscm {
+
+namespace {
+
+constexpr int kBpNT = 256;
+
+template <int M>
+__global__ __launch_bounds__(kBpNT) void bp_power_kernel(const ChunkInfo* __restrict__ chunks,
+                                                         const RowInfo* __restrict__ rows,
+                                                         const float2* __restrict__ x,
+                                                         const double2* __restrict__ W,
+                                                         double* __restrict__ part) {
+  const ChunkInfo ck = chunks[blockIdx.x];
+  const RowInfo ri = rows[ck.row];
+  const int t = threadIdx.x;
+  __shared__ double2 sW[M][M];
+  __shared__ double red[M][kBpNT / 64];
+  if (t < M * M) sW[t / M][t % M] = W[ri.rp_off + t];
+  __syncthreads();
+  double acc[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) acc[m] = 0.0;
+  for (int jj = t; jj < ck.len; jj += kBpNT) {
+    const float2* xp = x + ri.x_off + (long long)(ck.start + jj) * M;
+    double xr[M], xi[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      const float2 v = xp[n];
+      xr[n] = v.x;
+      xi[n] = v.y;
+    }
+    asm volatile("" ::: "memory");  // keep W in LDS (re-read per bin)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int n = 0; n < M; ++n) {
+        yr = fma(sW[m][n].x, xr[n], fma(-sW[m][n].y, xi[n], yr));
+        yi = fma(sW[m][n].x, xi[n], fma(sW[m][n].y, xr[n], yi));
+      }
+      acc[m] = fma(yr, yr, fma(yi, yi, acc[m]));
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double s = wave_sum_d(acc[m]);
+    if ((t & 63) == 0) red[m][t >> 6] = s;
+  }
+  __syncthreads();
+  if (t < M) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBpNT / 64; ++w) s += red[t][w];
+    part[(long long)ck.part * MAXM + t] = s;
+  }
+}
+
+// Smallest eigenvalue of a Hermitian n x n matrix (n <= 7) held in LDS, by
+// cyclic complex Jacobi rotations; one lane.
+__device__ double jacobi_min_eig(double2 (*H)[MAXM], int n) {
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int p = 0; p < n; ++p) {
+      dia += H[p][p].x * H[p][p].x;
+      for (int q = p + 1; q < n; ++q) off += H[p][q].x * H[p][q].x + H[p][q].y * H[p][q].y;
+    }
+    if (off <= 1e-30 * dia) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double2 apq = H[p][q];
+        const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+        if (mag < 1e-300) continue;
+        // phase: make H[p][q] real (column q times conj(ph), row q times ph)
+        const double2 ph = make_double2(apq.x / mag, apq.y / mag);
+        for (int r = 0; r < n; ++r) {
+          if (r == q) continue;
+          H[r][q] = zmul(H[r][q], zconj(ph));
+          H[q][r] = zconj(H[r][q]);
+        }
+        // real rotation zeroing the (p, q) entry
+        const double a = H[p][p].x, bq = H[q][q].x;
+        const double th = (bq - a) / (2.0 * mag);
+        const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
+        for (int r = 0; r < n; ++r) {
+          if (r == p || r == q) continue;
+          const double2 rp = H[r][p], rq = H[r][q];
+          const double2 np_ = make_double2(cs * rp.x - sn * rq.x, cs * rp.y - sn * rq.y);
+          const double2 nq_ = make_double2(sn * rp.x + cs * rq.x, sn * rp.y + cs * rq.y);
+          H[r][p] = np_;
+          H[p][r] = zconj(np_);
+          H[r][q] = nq_;
+          H[q][r] = zconj(nq_);
+        }
+        H[p][p] = make_double2(a - tt * mag, 0.0);
+        H[q][q] = make_double2(bq + tt * mag, 0.0);
+        H[p][q] = make_double2(0.0, 0.0);
+        H[q][p] = make_double2(0.0, 0.0);
+      }
+  }
+  double mn = H[0][0].x;
+  for (int p = 1; p < n; ++p) mn = fmin(mn, H[p][p].x);
+  return mn;
+}
+
+template <int M>
+__global__ __launch_bounds__(64) void bp_row_kernel(const int* __restrict__ row_list,
+                                                    const RowInfo* __restrict__ rows,
+                                                    const double2* __restrict__ W,
+                                                    const int* __restrict__ target,
+                                                    const double* __restrict__ part,
+                                                    double2* __restrict__ a_out,
+                                                    double2* __restrict__ rp_out,
+                                                    double2* __restrict__ b_out,
+                                                    double* __restrict__ p_out,
+                                                    float* __restrict__ lam0_out,
+                                                    unsigned* __restrict__ status) {
+  const int row = row_list[blockIdx.x];
+  const RowInfo ri = rows[row];
+  const int t = threadIdx.x;
+  const int i = t / M, j = t % M;
+  const bool ent = t < M * M;
+  const int nh = target[row];
+  __shared__ double2 aug[M][2 * M];
+  __shared__ double sp[M];
+  __shared__ int spiv;
+  __shared__ double2 G[MAXM][MAXM];
+  __shared__ unsigned sflag;
+  if (t == 0) sflag = 0u;
+  if (t < M) {  // p_m = mean_j |y_m|^2
+    double s = 0.0;
+    for (int k = 0; k < ri.nparts; ++k) s += part[(long long)(ri.part_off + k) * MAXM + t];
+    sp[t] = s / (double)ri.J;
+    p_out[(long long)row * MAXM + t] = sp[t];
+  }
+  if (ent) {
+    aug[i][j] = W[ri.rp_off + t];
+    aug[i][M + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  wave_sync();
+  // Gauss-Jordan with partial pivoting: aug = [W | I] -> [I | W^{-1}]
+  for (int k = 0; k < M; ++k) {
+    if (t == 0) {
+      int best = k;
+      double bm = -1.0;
+      for (int r = k; r < M; ++r) {
+        const double m2 = aug[r][k].x * aug[r][k].x + aug[r][k].y * aug[r][k].y;
+        if (m2 > bm) {
+          bm = m2;
+          best = r;
+        }
+      }
+      if (!(bm > 0.0)) sflag |= ST_NOT_PSD;  // singular demixing matrix
+      spiv = best;
+    }
+    wave_sync();
+    const int pr = spiv;
+    if (pr != k && t < 2 * M) {  // swap rows k and pr
+      const double2 tmp = aug[k][t];
+      aug[k][t] = aug[pr][t];
+      aug[pr][t] = tmp;
+    }
+    wave_sync();
+    const double2 pv = aug[k][k];
+    const double pm = pv.x * pv.x + pv.y * pv.y;
+    const double2 ip = pm > 0.0 ? make_double2(pv.x / pm, -pv.y / pm) : make_double2(0.0, 0.0);
+    double2 f = make_double2(0.0, 0.0), r1 = f, r2 = f;
+    if (ent) {
+      f = aug[i][k];
+      r1 = aug[k][j];
+      r2 = aug[k][M + j];
+    }
+    wave_sync();
+    if (ent) {
+      const double2 n1 = zmul(r1, ip), n2 = zmul(r2, ip);
+      if (i == k) {
+        aug[k][j] = n1;
+        aug[k][M + j] = n2;
+      } else {
+        const double2 d1 = zmul(f, n1), d2 = zmul(f, n2);
+        aug[i][j] = make_double2(aug[i][j].x - d1.x, aug[i][j].y - d1.y);
+        aug[i][M + j] = make_double2(aug[i][M + j].x - d2.x, aug[i][M + j].y - d2.y);
+      }
+    }
+    wave_sync();
+  }
+  // A = W^{-1} = aug[:, M:]; column m of A is aug[.][M + m]
+  if (ent) {  // R' = sum_{m != nh} p_m a_m a_m^H
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (m == nh) continue;
+      const double2 v = zmul(aug[i][M + m], zconj(aug[j][M + m]));
+      s.x += sp[m] * v.x;
+      s.y += sp[m] * v.y;
+    }
+    rp_out[ri.rp_off + t] = s;
+  }
+  if (t < M) {
+    a_out[ri.a_off + t] = aug[t][M + nh];
+    // b = w_nh / |w_nh|, w_nh = conj of row nh of W
+    double nw = 0.0;
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      const double2 v = W[ri.rp_off + nh * M + n];
+      nw += v.x * v.x + v.y * v.y;
+    }
+    const double2 w = W[ri.rp_off + nh * M + t];
+    const double inw = nw > 0.0 ? 1.0 / sqrt(nw) : 0.0;
+    b_out[ri.a_off + t] = make_double2(w.x * inw, -w.y * inw);
+  }
+  if (lam0_out != nullptr) {
+    // Gram matrix of the noise steering vectors, weighted by sqrt(p)
+    const int n1 = M - 1;
+    if (t < n1 * n1) {
+      const int k = t / n1, l = t % n1;
+      const int mk = k < nh ? k : k + 1, ml = l < nh ? l : l + 1;
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double2 v = zmulc(aug[r][M + mk], aug[r][M + ml]);
+        s.x += v.x;
+        s.y += v.y;
+      }
+      const double w = sqrt(sp[mk] * sp[ml]);
+      G[k][l] = make_double2(w * s.x, w * s.y);
+    }
+    wave_sync();
+    if (t == 0) lam0_out[row] = (float)jacobi_min_eig(G, n1);
+  }
+  if (t == 0 && sflag) atomicOr(status + row, sflag);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBpNT) void bp_ru_kernel(const ChunkInfo* __restrict__ chunks,
+                                                      const RowInfo* __restrict__ rows,
+                                                      const float2* __restrict__ x,
+                                                      const double2* __restrict__ W,
+                                                      const int* __restrict__ target,
+                                                      const double* __restrict__ p,
+                                                      float* __restrict__ ru0) {
+  const ChunkInfo ck = chunks[blockIdx.x];
+  const RowInfo ri = rows[ck.row];
+  const int t = threadIdx.x;
+  const int nh = target[ck.row];
+  __shared__ double2 sW[M][M];
+  __shared__ double sip[M];
+  if (t < M * M) sW[t / M][t % M] = W[ri.rp_off + t];
+  if (t < M) {
+    const double pm = p[(long long)ck.row * MAXM + t];
+    sip[t] = (t != nh && pm > 0.0) ? 1.0 / pm : 0.0;
+  }
+  __syncthreads();
+  for (int jj = t; jj < ck.len; jj += kBpNT) {
+    const float2* xp = x + ri.x_off + (long long)(ck.start + jj) * M;
+    double xr[M], xi[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      const float2 v = xp[n];
+      xr[n] = v.x;
+      xi[n] = v.y;
+    }
+    asm volatile("" ::: "memory");  // keep W in LDS (re-read per bin)
+    double e = 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int n = 0; n < M; ++n) {
+        yr = fma(sW[m][n].x, xr[n], fma(-sW[m][n].y, xi[n], yr));
+        yi = fma(sW[m][n].x, xi[n], fma(sW[m][n].y, xr[n], yi));
+      }
+      e = fma(fma(yr, yr, yi * yi), sip[m], e);
+    }
+    ru0[ri.bin_off + ck.start + jj] = (float)(e / (double)M);
+  }
+}
+
+}  // namespace
+
+void launch_backproject(hipStream_t s, int M, int nchunks_m, const ChunkInfo* chunks_m,
+                        int nrows_m, const int* rows_m_list, const RowInfo* rows, const float2* x,
+                        const double2* W, const int* target, double* part, double* p,
+                        double2* a_out, double2* rp_out, double2* b_out, float* ru0,
+                        float* lam0, unsigned* status, int stage) {
+  switch (M) {
+#define RCSCM_BP(MM)                                                                           \
+  case MM:                                                                                     \
+    if (stage == 0 && nchunks_m > 0)                                                           \
+      hipLaunchKernelGGL(bp_power_kernel<MM>, dim3(nchunks_m), dim3(kBpNT), 0, s, chunks_m,    \
+                         rows, x, W, part);                                                    \
+    if (stage == 1 && nrows_m > 0)                                                             \
+      hipLaunchKernelGGL(bp_row_kernel<MM>, dim3(nrows_m), dim3(64), 0, s, rows_m_list, rows,   \
+                         W, target,                                                            \
+                         part, a_out, rp_out, b_out, p, lam0, status);                        \
+    if (stage == 2 && nchunks_m > 0 && ru0 != nullptr)                                         \
+      hipLaunchKernelGGL(bp_ru_kernel<MM>, dim3(nchunks_m), dim3(kBpNT), 0, s, chunks_m, rows, \
+                         x, W, target, p, ru0);                                                \
+    break;
+    RCSCM_BP(2)
+    RCSCM_BP(3)
+    RCSCM_BP(4)
+    RCSCM_BP(5)
+    RCSCM_BP(6)
+    RCSCM_BP(7)
+    RCSCM_BP(8)
+#undef RCSCM_BP
+    default: break;
+  }
+}
+
+}  // namespace rcscm

@@ -54,6 +54,8 @@ struct rcscm_ctx {
   std::vector<ChunkInfo> h_chunks;
   // chunk ranges per microphone count (chunks sorted by M in d_chunks_m)
   std::vector<std::pair<int, int>> m_range = std::vector<std::pair<int, int>>(RCSCM_MAX_M + 1, {0, 0});
+  // rows grouped by microphone count (d_rows_m)
+  std::vector<std::pair<int, int>> mrow_range = std::vector<std::pair<int, int>>(RCSCM_MAX_M + 1, {0, 0});
   struct ResClass {
     int nt, bpl, count, offset;
   };
@@ -79,6 +81,11 @@ struct rcscm_ctx {
   double* d_objpart = nullptr;
   float* d_uhat = nullptr;
   unsigned* d_chunk_status = nullptr;
+  int* d_rows_m = nullptr;
+  // back-projection scratch (allocated on first use)
+  double* d_bp_part = nullptr;
+  double* d_bp_p = nullptr;
+  int* d_bp_target = nullptr;
   const float2* x_borrowed = nullptr;
   // checkpoints of the last iterate() call
   float* d_ck_rh = nullptr;
@@ -363,6 +370,16 @@ static rcscm_status build_tables(rcscm_ctx* c) {
   RCSCM_TRY(c->alloc(&c->d_chunks, c->nchunks, "chunks"));
   RCSCM_TRY(c->alloc(&c->d_chunks_m, c->nchunks, "chunks by M"));
   RCSCM_TRY(c->alloc(&c->d_row_list, row_list.size(), "row list"));
+  std::vector<int> rows_m;
+  for (int m = 2; m <= RCSCM_MAX_M; ++m) {
+    const int start = (int)rows_m.size();
+    for (int r = 0; r < c->nrows; ++r)
+      if (c->h_rows[r].M == m) rows_m.push_back(r);
+    c->mrow_range[m] = {start, (int)rows_m.size() - start};
+  }
+  RCSCM_TRY(c->alloc(&c->d_rows_m, rows_m.size(), "rows by M"));
+  RCSCM_HIP(c, hipMemcpy(c->d_rows_m, rows_m.data(), sizeof(int) * rows_m.size(),
+                         hipMemcpyHostToDevice));
   RCSCM_HIP(c, hipMemcpy(c->d_rows, c->h_rows.data(), sizeof(RowInfo) * c->nrows,
                          hipMemcpyHostToDevice));
   RCSCM_HIP(c, hipMemcpy(c->d_chunks, c->h_chunks.data(), sizeof(ChunkInfo) * c->nchunks,
@@ -388,6 +405,8 @@ static rcscm_status alloc_workspace(rcscm_ctx* c) {
   RCSCM_TRY(c->alloc(&c->d_part[1], c->nchunks, "partial sums"));
   RCSCM_TRY(c->alloc(&c->d_status, c->nrows, "status"));
   RCSCM_TRY(c->alloc(&c->d_chunk_status, c->nchunks, "chunk status"));
+  RCSCM_HIP(c, hipMemset(c->d_status, 0, sizeof(unsigned) * c->nrows));
+  RCSCM_HIP(c, hipMemset(c->d_chunk_status, 0, sizeof(unsigned) * c->nchunks));
   RCSCM_TRY(c->alloc(&c->d_objpart, c->nchunks, "objective partials"));
   if (c->p.rule == RCSCM_RULE_NAIVE) {
     long long maxMM = 0;
@@ -649,7 +668,6 @@ rcscm_status rcscm_set_state(rcscm_ctx* c, const float* rh, const float* ru, con
 rcscm_status rcscm_sync(rcscm_ctx* c) {
   if (!c) return RCSCM_EINVAL;
   RCSCM_HIP(c, hipStreamSynchronize(c->stream));
-  if (!c->inited) return RCSCM_OK;
   std::vector<unsigned> st(c->nrows), cst(c->nchunks);
   RCSCM_HIP(c, hipMemcpy(st.data(), c->d_status, sizeof(unsigned) * c->nrows,
                          hipMemcpyDeviceToHost));
@@ -715,6 +733,40 @@ rcscm_status rcscm_backward(rcscm_ctx* c, const void* x, const void* grad_s_hat,
                     grad_rh0, grad_lam0);
     RCSCM_HIP(c, hipGetLastError());
   }
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_backproject(rcscm_ctx* c, const void* x, const void* W, const int* target,
+                               void* a, void* Rp, void* b, float* ru0, float* lam0) {
+  if (!c) return RCSCM_EINVAL;
+  if (!x || !W || !target || !a || !Rp || !b)
+    return c->fail(RCSCM_EINVAL, "x, W, target, a, Rp and b must not be NULL");
+  for (int u = 0; u < c->U; ++u)
+    if (target[u] < 0 || target[u] >= c->M[u])
+      return c->fail(RCSCM_EINVAL, "target index out of range (utterance " + std::to_string(u) + ")");
+  if (!c->d_bp_part) {
+    RCSCM_TRY(c->alloc(&c->d_bp_part, (size_t)c->nchunks * MAXM, "back-projection partials"));
+    RCSCM_TRY(c->alloc(&c->d_bp_p, (size_t)c->nrows * MAXM, "back-projection powers"));
+    RCSCM_TRY(c->alloc(&c->d_bp_target, (size_t)c->nrows, "target indices"));
+  }
+  std::vector<int> tg(c->nrows);
+  for (int r = 0; r < c->nrows; ++r) tg[r] = target[c->h_rows[r].utt];
+  hipStream_t s = c->stream;
+  RCSCM_HIP(c, hipMemcpyAsync(c->d_bp_target, tg.data(), sizeof(int) * c->nrows,
+                              hipMemcpyHostToDevice, s));
+  RCSCM_HIP(c, hipStreamSynchronize(s));  // tg is a host temporary
+  for (int stage = 0; stage < 3; ++stage)
+    for (int m = 2; m <= RCSCM_MAX_M; ++m) {
+      const auto cr = c->m_range[m];
+      const auto rr = c->mrow_range[m];
+      if (rr.second == 0) continue;
+      launch_backproject(s, m, cr.second, c->d_chunks_m + cr.first, rr.second,
+                         c->d_rows_m + rr.first, c->d_rows, static_cast<const float2*>(x),
+                         static_cast<const double2*>(W), c->d_bp_target, c->d_bp_part, c->d_bp_p,
+                         static_cast<double2*>(a), static_cast<double2*>(Rp),
+                         static_cast<double2*>(b), ru0, lam0, c->d_status, stage);
+      RCSCM_HIP(c, hipGetLastError());
+    }
   return RCSCM_OK;
 }
 

@@ -139,6 +139,14 @@ void launch_first_stage(hipStream_t s, int M, int bpl, int nrows, const int* row
                         const float2* x, float* rh, float* ru, float* lam, float alpha,
                         float beta, int K, unsigned* status);
 
+// Back-projection (eq. (11)) and initialisation (eqs. (22), (23)); stage 0:
+// powers p_m per chunk, stage 1: per row (a, R', b, lambda_0), stage 2: r^u_0.
+void launch_backproject(hipStream_t s, int M, int nchunks_m, const ChunkInfo* chunks_m,
+                        int nrows_m, const int* rows_m_list, const RowInfo* rows, const float2* x,
+                        const double2* W, const int* target, double* part, double* p,
+                        double2* a_out, double2* rp_out, double2* b_out, float* ru0,
+                        float* lam0, unsigned* status, int stage);
+
 // Adjoint of the RESIDENT/STREAM accelerated forward (checkpointed).
 void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_list,
                      const RowInfo* rows, const RowConstF* rcf, const RowConstD* rcd,

@@ -60,6 +60,7 @@ _SIGS = {
     "rcscm_workspace_bytes": (ctypes.c_size_t, [_I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                                 ctypes.POINTER(Params)]),
     "rcscm_get_schedule": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "rcscm_backproject": (_I, [_P, _P, _P, ctypes.POINTER(_I), _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -243,6 +244,25 @@ class Context:
         _check(lib().rcscm_backward(self._h, _ptr(x), _ptr(grad_s_hat), _ptr(gx), _ptr(grh),
                                     _ptr(glam)), self._h)
         return gx, grh, glam
+
+    def backproject(self, x: torch.Tensor, W: torch.Tensor, target, want_ru0=True,
+                    want_lam0=True):
+        """a, R', b (and r^u_0, lambda_0) from demixing matrices W (eq. (11), eqs. (22)-(23))."""
+        dev = self.device
+        na = sum(self.I * m for m in self.Ms)
+        nr = sum(self.I * m * m for m in self.Ms)
+        if W.dtype != torch.complex128 or W.numel() != nr:
+            raise ValueError(f"W must be complex128 with {nr} elements")
+        tg = [int(target)] * self.U if isinstance(target, int) else [int(t) for t in target]
+        a = torch.empty(na, dtype=torch.complex128, device=dev)
+        b = torch.empty(na, dtype=torch.complex128, device=dev)
+        Rp = torch.empty(nr, dtype=torch.complex128, device=dev)
+        ru0 = torch.empty(self.nbins, dtype=torch.float32, device=dev) if want_ru0 else None
+        lam0 = torch.empty(self.nrows, dtype=torch.float32, device=dev) if want_lam0 else None
+        T = (ctypes.c_int * self.U)(*tg)
+        _check(lib().rcscm_backproject(self._h, _ptr(x), _ptr(W), T, _ptr(a), _ptr(Rp), _ptr(b),
+                                       _ptr(ru0), _ptr(lam0)), self._h)
+        return a, Rp, b, ru0, lam0
 
     def schedule(self):
         s, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
