@@ -6,8 +6,10 @@ iterations, synthetic model-drawn STFT data (sinc-coherence diffuse noise of a
 4-mic linear array, 5 cm spacing, 16 kHz), complex64 observations.
 
 One step = the whole hot path on one batch, inputs already in HBM:
-  FP64 per-frequency setup + per-bin precomputation (init),
-  K accelerated iterations (iterate), Wiener-filter extraction (extract).
+  FP64 per-frequency setup + per-bin precomputation, K accelerated
+  iterations, Wiener-filter extraction - one rcscm_run call (a single fused
+  launch per row class).  The same work as three calls (rcscm_init,
+  rcscm_iterate, rcscm_extract) is timed too, for the per-phase breakdown.
 value = I*J*K*steps / wall time of the timed steps (TF-bin updates/s).
 
 Also reported on the same JSON line: the naive-rule GPU rate on the same
@@ -38,8 +40,14 @@ STREAM_BYTES_PER_UPDATE = 36
 PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1908_01964_amd/csrc/accel.hip", "paper_1908_01964_amd/csrc/accel_common.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "accel_resident_sinc_M4_I513_J1000_K20_traffic.json")
+# Fused launch (rcscm_run), writes per bin: tau^ax, sigma^bx (16), nu (4), r^h, r^u (8) to the
+# workspace, r^h, r^u (8) and s_hat (8) to the caller; reads x (8M).
+FUSED_WRITE_BYTES_PER_BIN = 44
+KERNEL_SOURCES = ["paper_1908_01964_amd/csrc/fused.hip", "paper_1908_01964_amd/csrc/init_common.h",
+                  "paper_1908_01964_amd/csrc/resident_loop.h",
+                  "paper_1908_01964_amd/csrc/accel_common.h",
+                  "paper_1908_01964_amd/csrc/small_linalg.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "accel_fused_sinc_M4_I513_J1000_K20_traffic.json")
 
 
 def kernel_sha():
@@ -165,6 +173,25 @@ def time_steps(ctx, inputs, out, K, steps, warmup, torch):
     return wall, phases
 
 
+def time_run(ctx, inputs, out, K, steps, warmup, torch):
+    """Times the single-call step rcscm_run (setup, precompute, K iterations, extraction)."""
+    x, a, Rp, b = inputs
+    for _ in range(warmup):
+        ctx.run(x, a, Rp, b, K, out=out)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for s in range(steps):
+        ctx.run(x, a, Rp, b, K, out=out)
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[s].elapsed_time(ev[s + 1]) * 1e3 for s in range(steps)]  # microseconds
+    return wall, sum(per) / steps
+
+
 def load_workload(wid):
     """(I, Js, Ms, K, problems, label) of a named workload."""
     from synth import CONFIGS, batch_shapes, batch_utterance, config
@@ -195,6 +222,8 @@ def main():
     ap.add_argument("--naive-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=0, help="0 = enough runs for >= 10 s of CPU work")
+    ap.add_argument("--modular", action="store_true",
+                    help="time the step as three calls (init, iterate, extract) instead of run")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -245,12 +274,26 @@ def main():
                ru=torch.empty(nbins, dtype=torch.float32, device=dev),
                lam=torch.empty(I * len(Js), dtype=torch.float32, device=dev),
                s_hat=torch.empty(nbins, dtype=torch.complex64, device=dev))
-    wall, phases = time_steps(ctx, inputs, out, K, args.steps, args.warmup, torch)
+    updates = nbins * K
+    # The step: one rcscm_run call (the fused single launch where the shape allows it) ...
+    fused = args.schedule != "stream" and max(Js) <= 8192 and not args.modular
+    run_us = None
+    if fused:
+        wall, run_us = time_run(ctx, inputs, out, K, args.steps, args.warmup, torch)
+        ctx.sync()
+        gpu_out = {k: v.cpu().numpy() for k, v in out.items()} if ref is not None else None
+    # ... and the same work as three calls (init, iterate, extract) for the phase breakdown
+    msteps = args.steps if not fused else max(10, args.steps // 4)
+    out_m = {k: torch.empty_like(v) for k, v in out.items()}
+    wall_m, phases = time_steps(ctx, inputs, out_m, K, msteps, min(args.warmup, 5), torch)
     ctx.sync()
     used = ctx.schedule()
-    updates = nbins * K
+    if not fused:
+        wall = wall_m * args.steps / msteps
+        gpu_out = {k: v.cpu().numpy() for k, v in out_m.items()} if ref is not None else None
     value = updates * args.steps / wall
-    gpu_out = {k: v.cpu().numpy() for k, v in out.items()} if ref is not None else None
+    modular = {"value": updates * msteps / wall_m, "ms_per_step": wall_m / msteps * 1e3,
+               "phases_us": phases, "schedule": used}
     ctx.close()
 
     naive = None
@@ -273,7 +316,18 @@ def main():
 
     # roofline of the dominant kernel
     it_us = phases["iterate"]
-    if used["schedule"] == "resident":
+    if fused:
+        achieved = FLOPS_PER_UPDATE * updates / (run_us * 1e-6) / 1e12
+        bytes_bin = 8 * Ms[0] + FUSED_WRITE_BYTES_PER_BIN if len(set(Ms)) == 1 else None
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                "traffic": load_traffic() if args.workload == 1 else None,
+                "kernel": "accel_fused_kernel", "launch_us": run_us,
+                "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": updates,
+                "hbm_GBps_algorithmic": (bytes_bin * nbins / (run_us * 1e-6) / 1e9
+                                         if bytes_bin else None),
+                "algorithmic_bytes_per_bin": bytes_bin}
+    elif used["schedule"] == "resident":
         achieved = FLOPS_PER_UPDATE * updates / (it_us * 1e-6) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
@@ -298,7 +352,8 @@ def main():
         "config": {"workload": label, "I": I, "J": Js if len(Js) > 1 else Js[0],
                    "M": Ms if len(Ms) > 1 else Ms[0], "K": K, "bins": nbins, "schedule": used,
                    "step": "init(setup+precompute)+iterate(K)+extract(s_hat)"},
-        "phases_us": phases,
+        "step_call": "rcscm_run (fused)" if fused else "rcscm_init + rcscm_iterate + rcscm_extract",
+        "modular": modular,
         "iterate_only_value": updates / (phases["iterate"] * 1e-6),
         "roofline": roof,
     }

@@ -159,6 +159,18 @@ rcscm_status rcscm_iterate(rcscm_ctx* ctx, int K);
  * (complex64, batch layout).  Any output pointer may be NULL.  Async. */
 rcscm_status rcscm_extract(rcscm_ctx* ctx, float* rh, float* ru, float* lam, void* s_hat);
 
+/* init + iterate(K) + extract in one call (same arguments and outputs as
+ * those three calls).  For the ACCEL rule with every J_u <= 8192, the F64
+ * lambda sum and no checkpoints, each row runs its whole path - FP64 setup,
+ * FP64 precomputation, K iterations, extraction - in one workgroup of one
+ * launch per (M, workgroup size) class, reading x once and writing the
+ * results once; otherwise the three calls are made in turn.  Leaves the
+ * context in the same state as the three calls (iterate/extract/objective
+ * may follow).  Asynchronous. */
+rcscm_status rcscm_run(rcscm_ctx* ctx, const void* x, const void* a, const void* Rp,
+                       const void* b, const float* rh0, const float* ru0, const float* lam0,
+                       int K, float* rh, float* ru, float* lam, void* s_hat);
+
 /* Replaces the state (device arrays in batch layout; none may be NULL).
  * Async.  Used to resume from a saved state. */
 rcscm_status rcscm_set_state(rcscm_ctx* ctx, const float* rh, const float* ru, const float* lam);

@@ -17,7 +17,7 @@
 //   iteration k-1 is recomputed from the stored state of iteration k-2
 //   (cheap arithmetic) instead of storing its intermediates.  HBM traffic
 //   per launch: 28 bytes read and 8 bytes written per bin.
-#include "accel_common.h"
+#include "resident_loop.h"
 
 namespace rcscm {
 
@@ -40,8 +40,6 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
   const int J = ri.J;
   const long long base = ri.bin_off;
   const int t = threadIdx.x;
-  const int wave = t >> 6;
-  const double invJ = 1.0 / (double)J;
 
   float4 ts[BPL];
   float vnu[BPL], vrh[BPL], vru[BPL];
@@ -60,40 +58,10 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
       vru[q] = 1.f;
     }
   }
-  float lam_t = lam[row];
   __shared__ uint64_t red[2][NW];
-  LamTerms Lt = lam_terms(rc, lam_t);
-
-  for (int k = 0; k < K; ++k) {
-    if (ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
-#pragma unroll
-      for (int q = 0; q < BPL; ++q) {
-        const int j = t + q * NT;
-        if (j < J) {
-          ck_rh[(long long)k * ck_sb + base + j] = vrh[q];
-          ck_ru[(long long)k * ck_sb + base + j] = vru[q];
-        }
-      }
-      if (t == 0) ck_lam[(long long)k * ck_sr + row] = lam_t;
-    }
-    LamAcc<LS> acc;
-    PhaseA A[BPL];
-#pragma unroll
-    for (int q = 0; q < BPL; ++q) {
-      A[q] = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
-      if (t + q * NT < J) acc.add(A[q].t);
-      vrh[q] = A[q].rh_new;
-    }
-    acc = wave_allreduce<LS>(acc);
-    if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
-    __syncthreads();
-    const float lam_n = slots_sum<LS, NW>(red[k & 1]).mean(invJ);
-    const LamTerms Ln = lam_terms(rc, lam_n);
-#pragma unroll
-    for (int q = 0; q < BPL; ++q) vru[q] = phase_b(ts[q], vnu[q], A[q], rc, Ln);
-    lam_t = lam_n;
-    Lt = Ln;
-  }
+  const float lam_t = resident_iterations<NT, BPL, LS>(ts, vnu, vrh, vru, rc, lam[row], row, J,
+                                                       base, K, inv_a2, beta_a2, red, ck_rh,
+                                                       ck_ru, ck_lam, ck_sb, ck_sr);
 
   bool bad = false;
 #pragma unroll

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -61,6 +62,10 @@ struct rcscm_ctx {
   };
   std::vector<ResClass> res_classes;
   std::vector<ResClass> first_classes;  // FIRST rule: nt field holds M
+  struct FusedClass {
+    int M, nt, bpl, count, offset;
+  };
+  std::vector<FusedClass> fused_classes;  // rcscm_run (empty: not available)
 
   Buffers mem;
   RowInfo* d_rows = nullptr;
@@ -94,6 +99,7 @@ struct rcscm_ctx {
   int ck_capacity = 0;
   int ck_K = -1;
   bool inited = false;
+  bool chunk_status_valid = false;  // chunk_status written by the last rcscm_init
   std::string err;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
@@ -364,6 +370,24 @@ static rcscm_status build_tables(rcscm_ctx* c) {
       row_list.insert(row_list.end(), kv.second.begin(), kv.second.end());
     }
   }
+  if (c->p.rule == RCSCM_RULE_ACCEL && maxJ <= kMaxResidentJ) {
+    std::map<std::tuple<int, int, int>, std::vector<int>> cls;  // (M, nt, bpl)
+    bool ok = true;
+    for (int r = 0; r < c->nrows && ok; ++r) {
+      int nt = 0, bpl = 0;
+      ok = fused_class(c->h_rows[r].J, &nt, &bpl);
+      cls[std::make_tuple(c->h_rows[r].M, nt, bpl)].push_back(r);
+    }
+    if (ok)
+      for (auto& kv : cls) {
+        c->fused_classes.push_back(rcscm_ctx::FusedClass{std::get<0>(kv.first),
+                                                         std::get<1>(kv.first),
+                                                         std::get<2>(kv.first),
+                                                         (int)kv.second.size(),
+                                                         (int)row_list.size()});
+        row_list.insert(row_list.end(), kv.second.begin(), kv.second.end());
+      }
+  }
   if (row_list.empty()) row_list.push_back(0);
   // device copies
   RCSCM_TRY(c->alloc(&c->d_rows, c->nrows, "rows"));
@@ -525,6 +549,7 @@ rcscm_status rcscm_init(rcscm_ctx* c, const void* x, const void* a, const void* 
   }
   c->x_borrowed = static_cast<const float2*>(x);
   c->inited = true;
+  c->chunk_status_valid = true;
   c->ck_K = -1;
   return RCSCM_OK;
 }
@@ -673,7 +698,8 @@ rcscm_status rcscm_sync(rcscm_ctx* c) {
                          hipMemcpyDeviceToHost));
   RCSCM_HIP(c, hipMemcpy(cst.data(), c->d_chunk_status, sizeof(unsigned) * c->nchunks,
                          hipMemcpyDeviceToHost));
-  for (int k = 0; k < c->nchunks; ++k) st[c->h_chunks[k].row] |= cst[k];
+  if (c->chunk_status_valid)
+    for (int k = 0; k < c->nchunks; ++k) st[c->h_chunks[k].row] |= cst[k];
   const unsigned order[] = {ST_NONFINITE_IN, ST_NOT_NULL, ST_NOT_PSD, ST_NONFINITE_STATE,
                             ST_LAM_NONPOS};
   for (unsigned bit : order) {
@@ -767,6 +793,60 @@ rcscm_status rcscm_backproject(rcscm_ctx* c, const void* x, const void* W, const
                          static_cast<double2*>(b), ru0, lam0, c->d_status, stage);
       RCSCM_HIP(c, hipGetLastError());
     }
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* Rp, const void* b,
+                       const float* rh0, const float* ru0, const float* lam0, int K, float* rh,
+                       float* ru, float* lam, void* s_hat) {
+  if (!c) return RCSCM_EINVAL;
+  if (K < 0) return c->fail(RCSCM_ESHAPE, "K must be >= 0");
+  if (!x || !a || !Rp || !b) return c->fail(RCSCM_EINVAL, "x, a, Rp and b must not be NULL");
+  const bool fused = !c->fused_classes.empty() && c->p.lamsum == RCSCM_LAMSUM_F64 &&
+                     !(c->p.flags & RCSCM_FLAG_CHECKPOINT);
+  if (!fused) {  // the same path as separate calls
+    RCSCM_TRY(rcscm_init(c, x, a, Rp, b, rh0, ru0, lam0));
+    RCSCM_TRY(rcscm_iterate(c, K));
+    return rcscm_extract(c, rh, ru, lam, s_hat);
+  }
+  c->lam_cur = 0;
+  FusedArgs A;
+  A.rows = c->d_rows;
+  A.x = static_cast<const float2*>(x);
+  A.a = static_cast<const double2*>(a);
+  A.Rp = static_cast<const double2*>(Rp);
+  A.b = static_cast<const double2*>(b);
+  A.rh0 = rh0;
+  A.ru0 = ru0;
+  A.lam0 = lam0;
+  A.rh_c = c->p.rh0;
+  A.ru_c = c->p.ru0;
+  A.lam_c = c->p.lam0;
+  A.rcd = c->d_rcd;
+  A.rcf = c->d_rcf;
+  A.rsf = c->d_rsf;
+  A.tsig = c->d_tsig;
+  A.nu = c->d_nu;
+  A.rh = c->d_rh;
+  A.ru = c->d_ru;
+  A.lam = c->d_lam[c->lam_cur];
+  A.status = c->d_status;
+  A.rh_out = rh;
+  A.ru_out = ru;
+  A.lam_out = lam;
+  A.s_hat = static_cast<float2*>(s_hat);
+  A.inv_a2 = (float)(1.0 / (c->p.alpha + 2.0));
+  A.beta_a2 = (float)(c->p.beta / (c->p.alpha + 2.0));
+  A.K = K;
+  c->chunk_status_valid = false;  // the fused kernel reports through status[row] only
+  for (const auto& cl : c->fused_classes) {
+    A.row_list = c->d_row_list + cl.offset;
+    launch_fused(c->stream, cl.M, cl.nt, cl.bpl, cl.count, A);
+    RCSCM_HIP(c, hipGetLastError());
+  }
+  c->x_borrowed = static_cast<const float2*>(x);
+  c->inited = true;
+  c->ck_K = -1;
   return RCSCM_OK;
 }
 

@@ -1,0 +1,139 @@
+// rcscm_run: the whole path of one row in one workgroup and one launch -
+// per-row FP64 setup, per-bin FP64 precomputation into registers, K
+// second-stage iterations (Algorithm 2) in registers, Wiener-filter
+// extraction.  HBM traffic per bin: x (8M bytes) read once; tau^ax, sigma^bx,
+// nu, r^h, r^u (28 bytes) and s_hat (8) written once, plus the caller's
+// copies of r^h, r^u.  The setup of wave 0 overlaps the first x loads of all
+// waves.  One launch per (M, workgroup size, bins per lane) class.
+#include "init_common.h"
+#include "resident_loop.h"
+
+namespace rcscm {
+
+namespace {
+
+template <int M, int NT, int BPL>
+__global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
+  constexpr int NW = NT / 64;
+  const int row = A.row_list[blockIdx.x];
+  const RowInfo ri = A.rows[row];
+  const int J = ri.J;
+  const long long base = ri.bin_off;
+  const int t = threadIdx.x;
+  __shared__ SetupLDS<M> L;
+  __shared__ uint64_t red[2][NW];
+  __shared__ unsigned cflag;
+
+  const bool al4 = (M & 1) == 0 && (ri.x_off & 1) == 0;
+  float2 xa[M], xb[M];
+  auto load_bin = [&](int q, float2(&xv)[M]) {
+    const int j = t + q * NT;
+    if (j < J) load_x<M>(A.x + ri.x_off + (long long)j * M, al4, xv);
+  };
+  load_bin(0, xa);
+  if (BPL > 1) load_bin(1, xb);
+  if (t == 0) cflag = 0u;
+
+  if (t < 64) row_setup_wave<M>(A.Rp, A.a, A.b, ri, L);
+  __syncthreads();
+  write_row_constants<M>(L, row, ri, A.rcd, A.rcf, A.rsf, A.lam0, A.lam_c, A.lam, A.status);
+  const RowConstF rc = row_const_f<M>(L, ri);
+  const double inv_taa = L.taa > 0.0 ? 1.0 / L.taa : 0.0;
+
+  float4 ts[BPL];
+  float vnu[BPL], vrh[BPL], vru[BPL];
+  bool bad_x = false, bad_state = false;
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * NT;
+    if (j < J) {
+      precompute_bin<M>(xa, L, inv_taa, ts[q], vnu[q], bad_x);
+      A.tsig[base + j] = ts[q];
+      A.nu[base + j] = vnu[q];
+      vrh[q] = A.rh0 ? A.rh0[base + j] : A.rh_c;
+      vru[q] = A.ru0 ? A.ru0[base + j] : A.ru_c;
+      bad_state = bad_state || !(vrh[q] > 0.0f) || !(vru[q] > 0.0f) || !isfinite(vrh[q]) ||
+                  !isfinite(vru[q]);
+    } else {
+      ts[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      vnu[q] = 0.f;
+      vrh[q] = 1.f;
+      vru[q] = 1.f;
+    }
+    if (q + 1 < BPL) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) xa[m] = xb[m];
+      if (q + 2 < BPL) load_bin(q + 2, xb);
+    }
+  }
+  const float lam0 = A.lam0 ? A.lam0[row] : A.lam_c;
+  const float lam_fin = resident_iterations<NT, BPL, 0>(ts, vnu, vrh, vru, rc, lam0, row, J, base,
+                                                        A.K, A.inv_a2, A.beta_a2, red, nullptr,
+                                                        nullptr, nullptr, 0, 0);
+  const LamTerms Lf = lam_terms(rc, lam_fin);
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * NT;
+    if (j >= J) continue;
+    A.rh[base + j] = vrh[q];
+    A.ru[base + j] = vru[q];
+    if (A.rh_out) A.rh_out[base + j] = vrh[q];
+    if (A.ru_out) A.ru_out[base + j] = vru[q];
+    if (A.s_hat) A.s_hat[base + j] = s_hat_of(ts[q], vrh[q], vru[q], Lf);
+    bad_state = bad_state || !isfinite(vrh[q]) || !isfinite(vru[q]);
+  }
+  if (t == 0) {
+    A.lam[row] = lam_fin;
+    if (A.lam_out) A.lam_out[row] = lam_fin;
+    if (!(lam_fin > 0.0f) || !isfinite(lam_fin)) atomicOr(A.status + row, ST_LAM_NONPOS);
+  }
+  if (bad_x) atomicOr(&cflag, ST_NONFINITE_IN);
+  if (bad_state) atomicOr(&cflag, ST_NONFINITE_STATE);
+  __syncthreads();
+  if (t == 0 && cflag) atomicOr(A.status + row, cflag);
+}
+
+template <int M>
+void fused_launch_m(hipStream_t s, int nt, int bpl, int nrows, const FusedArgs& A) {
+#define RCSCM_FU(NTT, B)                                                                   \
+  if (nt == NTT && bpl == B) {                                                             \
+    hipLaunchKernelGGL((accel_fused_kernel<M, NTT, B>), dim3(nrows), dim3(NTT), 0, s, A); \
+    return;                                                                                \
+  }
+  RCSCM_FU(256, 1)
+  RCSCM_FU(256, 2)
+  RCSCM_FU(256, 4)
+  RCSCM_FU(256, 8)
+  RCSCM_FU(1024, 4)
+  RCSCM_FU(1024, 8)
+#undef RCSCM_FU
+}
+
+}  // namespace
+
+bool fused_class(int J, int* nt, int* bpl) {
+  const int cls[6][2] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {1024, 4}, {1024, 8}};
+  for (const auto& c : cls)
+    if (c[0] * c[1] >= J) {
+      *nt = c[0];
+      *bpl = c[1];
+      return true;
+    }
+  return false;
+}
+
+void launch_fused(hipStream_t s, int M, int nt, int bpl, int nrows, const FusedArgs& A) {
+  if (nrows <= 0) return;
+  switch (M) {
+    case 2: fused_launch_m<2>(s, nt, bpl, nrows, A); break;
+    case 3: fused_launch_m<3>(s, nt, bpl, nrows, A); break;
+    case 4: fused_launch_m<4>(s, nt, bpl, nrows, A); break;
+    case 5: fused_launch_m<5>(s, nt, bpl, nrows, A); break;
+    case 6: fused_launch_m<6>(s, nt, bpl, nrows, A); break;
+    case 7: fused_launch_m<7>(s, nt, bpl, nrows, A); break;
+    case 8: fused_launch_m<8>(s, nt, bpl, nrows, A); break;
+    default: break;
+  }
+}
+
+}  // namespace rcscm

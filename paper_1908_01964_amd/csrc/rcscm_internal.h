@@ -95,6 +95,38 @@ struct InitArgs {
 };
 void launch_init(hipStream_t s, int M, int nchunks, const InitArgs& args);
 
+// Fused single launch (rcscm_run): setup, precompute, K iterations and
+// extraction of each row in one workgroup.  Classes (nt, bpl) from fused_class.
+struct FusedArgs {
+  const int* row_list;
+  const RowInfo* rows;
+  const float2* x;
+  const double2* a;
+  const double2* Rp;
+  const double2* b;
+  const float* rh0;
+  const float* ru0;
+  const float* lam0;
+  float rh_c, ru_c, lam_c;
+  RowConstD* rcd;
+  RowConstF* rcf;
+  RowSpatialF* rsf;
+  float4* tsig;
+  float* nu;
+  float* rh;
+  float* ru;
+  float* lam;
+  unsigned* status;
+  float* rh_out;
+  float* ru_out;
+  float* lam_out;
+  float2* s_hat;
+  float inv_a2, beta_a2;
+  int K;
+};
+bool fused_class(int J, int* nt, int* bpl);
+void launch_fused(hipStream_t s, int M, int nt, int bpl, int nrows, const FusedArgs& A);
+
 // RESIDENT schedule: rows in row_list (all with J <= nt * bpl).
 bool resident_supported(int nt, int bpl);
 void launch_accel_resident(hipStream_t s, int nt, int bpl, int lamsum, int nrows,

@@ -1,0 +1,68 @@
+// The K-iteration loop of the RESIDENT schedule (one workgroup per row, BPL
+// bins per lane in registers), shared by the resident kernel and the fused
+// single-launch kernel.  Per iteration: phase A over the lane's bins, the
+// lambda frame sum (DPP within each wave, one LDS slot per wave, one barrier;
+// the slots are double-buffered so no second barrier is needed), phase B.
+#pragma once
+
+#include "accel_common.h"
+
+namespace rcscm {
+
+// Runs K iterations in place on (vrh, vru); returns the final lambda.  Bins
+// with frame index t + q*NT >= J do not enter the frame sum.  When ck_rh is
+// not null, theta at the start of every iteration is stored (checkpoints).
+template <int NT, int BPL, int LS>
+__device__ __forceinline__ float resident_iterations(
+    const float4 (&ts)[BPL], const float (&vnu)[BPL], float (&vrh)[BPL], float (&vru)[BPL],
+    const RowConstF& rc, float lam_t, int row, int J, long long base, int K, float inv_a2,
+    float beta_a2, uint64_t (*red)[NT / 64], float* __restrict__ ck_rh,
+    float* __restrict__ ck_ru, float* __restrict__ ck_lam, long long ck_sb, int ck_sr) {
+  constexpr int NW = NT / 64;
+  const int t = threadIdx.x;
+  const int wave = t >> 6;
+  const double invJ = 1.0 / (double)J;
+  LamTerms Lt = lam_terms(rc, lam_t);
+  for (int k = 0; k < K; ++k) {
+    if (ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
+#pragma unroll
+      for (int q = 0; q < BPL; ++q) {
+        const int j = t + q * NT;
+        if (j < J) {
+          ck_rh[(long long)k * ck_sb + base + j] = vrh[q];
+          ck_ru[(long long)k * ck_sb + base + j] = vru[q];
+        }
+      }
+      if (t == 0) ck_lam[(long long)k * ck_sr + row] = lam_t;
+    }
+    LamAcc<LS> acc;
+    PhaseA A[BPL];
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      A[q] = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
+      if (t + q * NT < J) acc.add(A[q].t);
+      vrh[q] = A[q].rh_new;
+    }
+    acc = wave_allreduce<LS>(acc);
+    if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
+    __syncthreads();
+    const float lam_n = slots_sum<LS, NW>(red[k & 1]).mean(invJ);
+    const LamTerms Ln = lam_terms(rc, lam_n);
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) vru[q] = phase_b(ts[q], vnu[q], A[q], rc, Ln);
+    lam_t = lam_n;
+    Lt = Ln;
+  }
+  return lam_t;
+}
+
+// Wiener-filter estimate s_hat = gamma rho^ax of one bin at (r^h, r^u) and
+// the lambda terms L (posterior mean of s, inside eq. (15)).
+__device__ __forceinline__ float2 s_hat_of(const float4 ts, float rh, float ru, const LamTerms& L) {
+  const float rx_re = fmaf(L.sp_re, ts.z, fmaf(-L.sp_im, ts.w, ts.x));
+  const float rx_im = fmaf(L.sp_re, ts.w, fmaf(L.sp_im, ts.z, ts.y));
+  const float g = rh / fmaf(rh, L.rho_aa, ru);
+  return make_float2(g * rx_re, g * rx_im);
+}
+
+}  // namespace rcscm

@@ -61,6 +61,7 @@ _SIGS = {
                                                 ctypes.POINTER(Params)]),
     "rcscm_get_schedule": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "rcscm_backproject": (_I, [_P, _P, _P, ctypes.POINTER(_I), _P, _P, _P, _P, _P]),
+    "rcscm_run": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _I, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -214,6 +215,22 @@ class Context:
                 out["s_hat"] = torch.empty(self.nbins, dtype=torch.complex64, device=dev)
         _check(lib().rcscm_extract(self._h, _ptr(out.get("rh")), _ptr(out.get("ru")),
                                    _ptr(out.get("lam")), _ptr(out.get("s_hat"))), self._h)
+        return out
+
+    def run(self, x, a, Rp, b, K: int, rh0=None, ru0=None, lam0=None, out=None, s_hat=True):
+        """init + iterate(K) + extract in one call (a single fused launch where possible)."""
+        self._check_sizes(x, a, Rp, b, rh0, ru0, lam0)
+        dev = self.device
+        if out is None:
+            out = dict(rh=torch.empty(self.nbins, dtype=torch.float32, device=dev),
+                       ru=torch.empty(self.nbins, dtype=torch.float32, device=dev),
+                       lam=torch.empty(self.nrows, dtype=torch.float32, device=dev))
+            if s_hat:
+                out["s_hat"] = torch.empty(self.nbins, dtype=torch.complex64, device=dev)
+        _check(lib().rcscm_run(self._h, _ptr(x), _ptr(a), _ptr(Rp), _ptr(b), _ptr(rh0), _ptr(ru0),
+                               _ptr(lam0), int(K), _ptr(out.get("rh")), _ptr(out.get("ru")),
+                               _ptr(out.get("lam")), _ptr(out.get("s_hat"))), self._h)
+        self._keep = [x]
         return out
 
     def set_state(self, rh: torch.Tensor, ru: torch.Tensor, lam: torch.Tensor):

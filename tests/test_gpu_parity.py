@@ -223,6 +223,64 @@ def test_config1_full_size_naive_sampled_rows():
     assert all(v < 1e-3 for v in e.values()), e
 
 
+def _gpu_run_fused(probs, K, **params):
+    from helpers import split
+    from paper_1908_01964_amd import Context, to_device
+    probs = probs if isinstance(probs, list) else [probs]
+    x, a, Rp, b = to_device(probs)
+    I = probs[0].x.shape[0]
+    Js = [p.x.shape[1] for p in probs]
+    ctx = Context(I, Js, [p.x.shape[2] for p in probs], **params)
+    out = ctx.run(x, a, Rp, b, K)
+    ctx.sync()
+    res = split({k: v.cpu().numpy() for k, v in out.items()}, I, Js)
+    return res, ctx, (x, a, Rp, b)
+
+
+@pytest.mark.parametrize("M,J", [(2, 1), (3, 250), (4, 1000), (5, 1025), (6, 2047), (8, 3000),
+                                 (4, 8000)])
+def test_fused_run_vs_oracle(M, J):
+    p = make_problem(M, 3, J, config=450 + M, spatial="sinc" if M % 2 == 0 else "random",
+                     n_fft=8)
+    ref = oracle_accel(p, 12)
+    out, ctx, _ = _gpu_run_fused(p, 12)
+    ctx.close()
+    assert_close(out[0], ref, what=f"fused M={M} J={J}")
+
+
+def test_fused_run_equals_separate_calls(c0):
+    """Same per-bin code and reduction order as init + iterate + extract with 256-lane rows."""
+    out_f, ctx, _ = _gpu_run_fused(c0, 20)
+    ctx.close()
+    out_s = gpu_run(c0, 20, schedule="resident", block=256)
+    for k in ("rh", "ru", "lam", "s_hat"):
+        assert np.array_equal(out_f[0][k], out_s[0][k]), k
+
+
+def test_fused_run_then_continue_and_objective():
+    import torch
+    p = make_problem(4, 5, 300, config=460, spatial="sinc", n_fft=16)
+    out, ctx, inputs = _gpu_run_fused(p, 7)
+    ctx.iterate(5)
+    o2 = {k: v.cpu().numpy().reshape(-1) for k, v in ctx.extract().items()}
+    nlp = ctx.objective()
+    ctx.close()
+    ref = oracle_accel(p, 12)
+    assert_close({k: v.reshape(ref[k].shape) for k, v in o2.items()}, ref, what="run(7)+iterate(5)")
+    from oracle import objective as o_obj
+    r_nlp = o_obj.nlp(p.x, p.a, p.Rp, p.b, ref["rh"], ref["ru"], ref["lam"], ALPHA, BETA)
+    assert abs(nlp - r_nlp) <= 1e-5 * abs(r_nlp) + 1e-3
+
+
+def test_fused_run_ragged_batch():
+    from synth import batch_utterance
+    probs = [batch_utterance(u, I=9) for u in (4, 7, 16, 0)]  # J = 227, 336, 3888, 2199
+    out, ctx, _ = _gpu_run_fused(probs, 20)
+    ctx.close()
+    for p, o in zip(probs, out):
+        assert_close(o, oracle_accel(p, 20), what=f"ragged J={p.J} M={p.M}")
+
+
 def _oracle_first(p, K):
     from oracle import accel as o_accel
     from oracle import extract as o_extract
