@@ -192,6 +192,49 @@ def time_run(ctx, inputs, out, K, steps, warmup, torch):
     return wall, sum(per) / steps
 
 
+def time_backproject(I, J, M, K, steps, torch):
+    """The step before the estimation: a, R', b, r^u_0 and lambda_0 from demixing matrices
+    (eq. (11), eqs. (22)-(23)) by rcscm_backproject, then rcscm_run from that initialisation,
+    on a determined M-source mixture of the same shape."""
+    import numpy as np
+
+    from paper_1908_01964_amd import Context
+    from synth.workloads import make_bss_problem
+    d = make_bss_problem(M, I, J, config=1, target=0, perturb=0.05)
+    x = torch.from_numpy(np.ascontiguousarray(d["x"]).reshape(-1)).cuda()
+    W = torch.from_numpy(np.ascontiguousarray(d["W"]).reshape(-1)).cuda()
+    ctx = Context(I, [J], [M])
+    nbins = I * J
+    out = dict(rh=torch.empty(nbins, dtype=torch.float32, device=x.device),
+               ru=torch.empty(nbins, dtype=torch.float32, device=x.device),
+               lam=torch.empty(I, dtype=torch.float32, device=x.device),
+               s_hat=torch.empty(nbins, dtype=torch.complex64, device=x.device))
+    for _ in range(3):
+        a, Rp, b, ru0, lam0 = ctx.backproject(x, W, 0)
+        ctx.run(x, a, Rp, b, K, ru0=ru0, lam0=lam0, out=out)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for s in range(steps):
+        ev[s][0].record()
+        a, Rp, b, ru0, lam0 = ctx.backproject(x, W, 0)
+        ev[s][1].record()
+        ctx.run(x, a, Rp, b, K, ru0=ru0, lam0=lam0, out=out)
+        ev[s][2].record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ctx.close()
+    bp_us = sum(e[0].elapsed_time(e[1]) for e in ev) / steps * 1e3
+    run_us = sum(e[1].elapsed_time(e[2]) for e in ev) / steps * 1e3
+    # x is read twice (source powers, then the noise image for r^u_0); r^u_0 written
+    bytes_bin = 16 * M + 4
+    return {"workload": f"determined {M}-source mixture, I={I}, J={J}, demixing W = A^-1 "
+                        f"(I + 0.05 E)", "backproject_us": bp_us,
+            "run_from_backprojection_us": run_us,
+            "pipeline_value": nbins * K / ((bp_us + run_us) * 1e-6),
+            "backproject_algorithmic_bytes_per_bin": bytes_bin,
+            "backproject_GBps_algorithmic": bytes_bin * nbins / (bp_us * 1e-6) / 1e9}
+
+
 def load_workload(wid):
     """(I, Js, Ms, K, problems, label) of a named workload."""
     from synth import CONFIGS, batch_shapes, batch_utterance, config
@@ -208,14 +251,92 @@ def load_workload(wid):
     return p.I, [p.J], [p.M], c["K"], [p], label
 
 
+def bench_adjoint(args):
+    """Forward (precompute, K checkpointed iterations, extraction) plus the hand-written
+    adjoint, on the M=4, I=513, J=1000 sinc-coherence utterance with K=10."""
+    import numpy as np
+    import torch
+
+    from paper_1908_01964_amd import Context, to_device
+    from synth import CONFIGS, config
+    p = config(3, with_truth=True)
+    I, J, M, K = p.I, p.J, p.M, CONFIGS[3]["K"]
+    x, a, Rp, b = to_device(p)
+    dev = x.device
+    nbins = I * J
+    s_true = torch.from_numpy(np.ascontiguousarray(p.s_true.reshape(-1)).astype(np.complex64)).to(dev)
+    rh0 = torch.ones(nbins, dtype=torch.float32, device=dev)
+    lam0 = torch.ones(I, dtype=torch.float32, device=dev)
+    ctx = Context(I, [J], [M], checkpoint=True)
+    out = dict(rh=torch.empty(nbins, dtype=torch.float32, device=dev),
+               ru=torch.empty(nbins, dtype=torch.float32, device=dev),
+               lam=torch.empty(I, dtype=torch.float32, device=dev),
+               s_hat=torch.empty(nbins, dtype=torch.complex64, device=dev))
+    gx = torch.empty_like(x)
+    grh = torch.empty(nbins, dtype=torch.float32, device=dev)
+    glam = torch.empty(I, dtype=torch.float32, device=dev)
+
+    def forward():
+        ctx.init(x, a, Rp, b, rh0=rh0, lam0=lam0)
+        ctx.iterate(K)
+        ctx.extract(out=out)
+
+    forward()
+    g = (2.0 * (out["s_hat"] - s_true)).contiguous()  # upstream gradient of sum |s_hat - s|^2
+    lib_backward = ctx.backward_into
+    for _ in range(args.warmup):
+        forward()
+        lib_backward(x, g, gx, grh, glam)
+    torch.cuda.synchronize()
+    steps = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        e = ev[s]
+        e[0].record()
+        forward()
+        e[1].record()
+        lib_backward(x, g, gx, grh, glam)
+        e[2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fw = sum(e[0].elapsed_time(e[1]) for e in ev) / steps * 1e3
+    bw = sum(e[1].elapsed_time(e[2]) for e in ev) / steps * 1e3
+    ctx.sync()
+    used = ctx.schedule()
+    ctx.close()
+    # algorithmic bytes of one adjoint launch per bin: tau^ax, sigma^bx, nu (20), K checkpoints
+    # of r^h, r^u (8K), final r^h, r^u (8), grad s_hat (8), x (8M) read; grad x (8M), grad r^h_0
+    # (4) written
+    bw_bytes = 20 + 8 * K + 8 + 8 + 8 * M + 8 * M + 4
+    achieved = bw_bytes * nbins / (bw * 1e-6) / 1e9
+    line = {
+        "metric": "TF-bin updates/s (M=4,I=513,J=1000) accel vs naive; % HBM peak; rel err vs FP64",
+        "value": nbins * K * steps / wall, "unit": "TF-bin updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sinc-coherence M=4 I=513 J=1000 K=10, forward + adjoint "
+                               "(loss sum |s_hat - s|^2)", "I": I, "J": J, "M": M, "K": K,
+                   "bins": nbins, "schedule": used,
+                   "step": "init+iterate(K, checkpointed)+extract+backward"},
+        "phases_us": {"forward": fw, "backward": bw},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "backward_kernel", "launch_us": bw,
+                     "algorithmic_bytes_per_bin": bw_bytes},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", type=int, default=1, choices=[1, 2, 4],
+    ap.add_argument("--workload", type=int, default=1, choices=[1, 2, 3, 4],
                     help="1 = the bench line (M=4, I=513, J=1000, K=20); 2 = ragged batch; "
-                         "4 = large instance")
+                         "3 = forward + adjoint (M=4, I=513, J=1000, K=10); 4 = large instance")
     ap.add_argument("--schedule", default="auto", choices=["auto", "resident", "stream"])
     ap.add_argument("--block", type=int, default=-1)
     ap.add_argument("--chunk", type=int, default=0)
@@ -236,6 +357,10 @@ def main():
     import numpy as np
 
     from synth import CONFIGS
+
+    if args.workload == 3:
+        bench_adjoint(args)
+        return
 
     cb, ref = None, None
     if args.workload == 1 and not args.no_cpu_baseline:
@@ -314,6 +439,10 @@ def main():
         first = {"value": updates * args.naive_steps / wall_f,
                  "ms_per_step": wall_f / args.naive_steps * 1e3, "phases_us": phases_f}
 
+    bp = None
+    if args.workload == 1 and args.naive_steps > 0:
+        bp = time_backproject(I, Js[0], Ms[0], K, max(10, args.steps // 4), torch)
+
     # roofline of the dominant kernel
     it_us = phases["iterate"]
     if fused:
@@ -364,6 +493,8 @@ def main():
     if first is not None:
         line["first_stage"] = first
         line["iterate_speedup_vs_first_stage"] = first["phases_us"]["iterate"] / phases["iterate"]
+    if bp is not None:
+        line["backproject"] = bp
     if cb is not None:
         line["cpu_baseline"] = cb
         errs = {}

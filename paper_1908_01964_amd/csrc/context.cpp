@@ -91,6 +91,7 @@ struct rcscm_ctx {
   double* d_bp_part = nullptr;
   double* d_bp_p = nullptr;
   int* d_bp_target = nullptr;
+  std::vector<int> h_bp_target;  // the target indices d_bp_target holds (per row)
   const float2* x_borrowed = nullptr;
   // checkpoints of the last iterate() call
   float* d_ck_rh = nullptr;
@@ -778,9 +779,12 @@ rcscm_status rcscm_backproject(rcscm_ctx* c, const void* x, const void* W, const
   std::vector<int> tg(c->nrows);
   for (int r = 0; r < c->nrows; ++r) tg[r] = target[c->h_rows[r].utt];
   hipStream_t s = c->stream;
-  RCSCM_HIP(c, hipMemcpyAsync(c->d_bp_target, tg.data(), sizeof(int) * c->nrows,
-                              hipMemcpyHostToDevice, s));
-  RCSCM_HIP(c, hipStreamSynchronize(s));  // tg is a host temporary
+  if (tg != c->h_bp_target) {  // upload only when the targets change
+    c->h_bp_target = tg;
+    RCSCM_HIP(c, hipMemcpyAsync(c->d_bp_target, c->h_bp_target.data(), sizeof(int) * c->nrows,
+                                hipMemcpyHostToDevice, s));
+    RCSCM_HIP(c, hipStreamSynchronize(s));  // the host vector may change on the next call
+  }
   for (int stage = 0; stage < 3; ++stage)
     for (int m = 2; m <= RCSCM_MAX_M; ++m) {
       const auto cr = c->m_range[m];

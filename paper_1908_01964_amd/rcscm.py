@@ -262,6 +262,13 @@ class Context:
                                     _ptr(glam)), self._h)
         return gx, grh, glam
 
+    def backward_into(self, x: torch.Tensor, grad_s_hat: torch.Tensor, grad_x=None, grad_rh0=None,
+                      grad_lam0=None):
+        """rcscm_backward into caller-allocated outputs (any of them may be None)."""
+        _check(lib().rcscm_backward(self._h, _ptr(x), _ptr(grad_s_hat), _ptr(grad_x),
+                                    _ptr(grad_rh0), _ptr(grad_lam0)), self._h)
+        return grad_x, grad_rh0, grad_lam0
+
     def backproject(self, x: torch.Tensor, W: torch.Tensor, target, want_ru0=True,
                     want_lam0=True):
         """a, R', b (and r^u_0, lambda_0) from demixing matrices W (eq. (11), eqs. (22)-(23))."""
