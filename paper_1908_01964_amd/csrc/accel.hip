@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       const int j = t + q * kStreamNT;
-      const float vnu = (j < len) ? nu[base + j] : 0.f;
+      const float vnu = (j < len) ? nu[base + j] * rc.invM : 0.f;
       const PhaseA A = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
       vrh[q] = A.rh_new;
       vru[q] = phase_b(ts[q], vnu, A, rc, Ln);
@@ -193,11 +193,17 @@ __global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
   if constexpr (START) {
     const LamTerms Lt = lam_terms(rc, lam_cur);
     LamAcc<LS> acc;
+    float tsum = 0.0f;  // F64 policy: the lane's terms in float, lanes in double
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       const PhaseA A = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
-      if (t + q * kStreamNT < len) acc.add(A.t);
+      const bool in = t + q * kStreamNT < len;
+      if constexpr (LS == 0)
+        tsum += in ? A.t : 0.0f;
+      else if (in)
+        acc.add(A.t);
     }
+    if constexpr (LS == 0) acc.s = (double)tsum;
     acc = wave_allreduce<LS>(acc);
     if ((t & 63) == 0) red[wave] = acc.pack();
     __syncthreads();
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(256) void objective_kernel(
   const RowInfo ri = rows[ck.row];
   const double taa = rcd[ck.row].t_aa;
   const double2 sab = rcd[ck.row].s_ab;
-  const double logpdet = rcd[ck.row].logpdet;
+  const double logpdet = log(rcd[ck.row].det_a) - log(rcd[ck.row].shift);  // log pdet(R')
   const double l = (double)lam[ck.row];
   const double M = (double)ri.M;
   const double sab2 = sab.x * sab.x + sab.y * sab.y;

@@ -9,7 +9,8 @@
 //   t      = gamma~ |sigma^ab|^2 + |e|^2 / r~u   (lambda <- mean_j t)          eq. (55)
 // and, after the frame sum has produced the new lambda,
 //   r^u    = (1/M) [ gamma~ r~u rho^aa + nu + |tau^ax - w tau^aa|^2 / tau^aa
-//                    + |e|^2 / lambda ],       w = gamma~ rho~ax.
+//                    + |e|^2 / lambda ],       w = gamma~ rho~ax,
+// with nu = tau^xx - |tau^ax|^2 / tau^aa from the precomputation.
 // The last line equals eq. (56): with y = x - w a, the statistic of eq. (44)
 // is U^ = gamma~ r~u a a^H + y y^H, and tr(R^{-1} U^) splits by the
 // pseudoinverse expansion eq. (26) into gamma~ r~u rho^aa + y^H (R')^+ y +
@@ -24,12 +25,16 @@ namespace rcscm {
 
 __device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
-// Per-row quantities that depend on one value of lambda.
+// Per-row quantities that depend on one value of lambda.  The *M members are
+// the same quantities divided by M, used by phase B.
 struct LamTerms {
   float il;      // 1 / lambda
   float rho_aa;  // tau^aa + |sigma^ab|^2 / lambda
   float sp_re;   // sigma^ab / lambda
   float sp_im;
+  float rho_aaM;  // rho^aa / M
+  float ilM;      // 1 / (M lambda)
+  float itaaM;    // 1 / (M tau^aa), 0 when tau^aa == 0
 };
 
 __device__ __forceinline__ LamTerms lam_terms(const RowConstF& rc, float lam) {
@@ -38,6 +43,9 @@ __device__ __forceinline__ LamTerms lam_terms(const RowConstF& rc, float lam) {
   L.rho_aa = fmaf(rc.sab2, L.il, rc.t_aa);
   L.sp_re = rc.sab_re * L.il;
   L.sp_im = rc.sab_im * L.il;
+  L.rho_aaM = L.rho_aa * rc.invM;
+  L.ilM = L.il * rc.invM;
+  L.itaaM = rc.inv_t_aa * rc.invM;
   return L;
 }
 
@@ -46,6 +54,8 @@ struct PhaseA {
   float rh_new, t, cg, w_re, w_im, E;
 };
 
+// With w = gamma~ rho~ax and cg = gamma~ r~u, eq. (54) reads
+// r^h = (cg + |w|^2 + beta) / (alpha + 2), and e = sigma^bx - conj(sigma^ab) w.
 __device__ __forceinline__ PhaseA phase_a(const float4 ts, float rh, float ru, const RowConstF& rc,
                                           const LamTerms& Lt, float inv_a2, float beta_a2) {
   PhaseA o;
@@ -53,28 +63,25 @@ __device__ __forceinline__ PhaseA phase_a(const float4 ts, float rh, float ru, c
   const float rx_re = fmaf(Lt.sp_re, ts.z, fmaf(-Lt.sp_im, ts.w, ts.x));
   const float rx_im = fmaf(Lt.sp_re, ts.w, fmaf(Lt.sp_im, ts.z, ts.y));
   const float g = rh * frcp(fmaf(rh, Lt.rho_aa, ru));
-  const float r2 = fmaf(rx_re, rx_re, rx_im * rx_im);
-  o.rh_new = fmaf(g * fmaf(g, r2, ru), inv_a2, beta_a2);
   o.w_re = g * rx_re;
   o.w_im = g * rx_im;
-  // e = sigma^bx - conj(sigma^ab) w
-  const float e_re = ts.z - fmaf(rc.sab_re, o.w_re, rc.sab_im * o.w_im);
-  const float e_im = ts.w - fmaf(rc.sab_re, o.w_im, -rc.sab_im * o.w_re);
+  o.cg = g * ru;
+  o.rh_new = fmaf(fmaf(o.w_re, o.w_re, fmaf(o.w_im, o.w_im, o.cg)), inv_a2, beta_a2);
+  const float e_re = fmaf(-rc.sab_re, o.w_re, fmaf(-rc.sab_im, o.w_im, ts.z));
+  const float e_im = fmaf(-rc.sab_re, o.w_im, fmaf(rc.sab_im, o.w_re, ts.w));
   o.E = fmaf(e_re, e_re, e_im * e_im);
   o.t = fmaf(g, rc.sab2, o.E * frcp(ru));
-  o.cg = g * ru;
   return o;
 }
 
-// Phase B of one bin: new r^u given the new lambda (terms Ln).
-__device__ __forceinline__ float phase_b(const float4 ts, float nu, const PhaseA& A,
+// Phase B of one bin: new r^u given the new lambda (terms Ln); nuM = nu / M.
+__device__ __forceinline__ float phase_b(const float4 ts, float nuM, const PhaseA& A,
                                          const RowConstF& rc, const LamTerms& Ln) {
   const float d_re = fmaf(-A.w_re, rc.t_aa, ts.x);
   const float d_im = fmaf(-A.w_im, rc.t_aa, ts.y);
-  float acc = fmaf(A.cg, Ln.rho_aa, nu);
-  acc = fmaf(fmaf(d_re, d_re, d_im * d_im), rc.inv_t_aa, acc);
-  acc = fmaf(A.E, Ln.il, acc);
-  return acc * rc.invM;
+  float acc = fmaf(A.cg, Ln.rho_aaM, nuM);
+  acc = fmaf(fmaf(d_re, d_re, d_im * d_im), Ln.itaaM, acc);
+  return fmaf(A.E, Ln.ilM, acc);
 }
 
 // ---- frame-sum accumulators for lambda --------------------------------------
@@ -91,16 +98,6 @@ struct LamAcc<0> {
   __device__ __forceinline__ LamAcc() : s(0.0) {}
   __device__ __forceinline__ void add(float t) { s += (double)t; }
   __device__ __forceinline__ void combine(const LamAcc& o) { s += o.s; }
-  __device__ __forceinline__ LamAcc shfl_xor(int off) const {
-    LamAcc r;
-    r.s = __shfl_xor(s, off, 64);
-    return r;
-  }
-  __device__ __forceinline__ LamAcc shfl(int lane) const {
-    LamAcc r;
-    r.s = __shfl(s, lane, 64);
-    return r;
-  }
   __device__ __forceinline__ uint64_t pack() const { return __double_as_longlong(s); }
   __device__ __forceinline__ static LamAcc unpack(uint64_t v) {
     LamAcc r;
@@ -127,18 +124,6 @@ struct LamAcc<1> {
     c = c + o.c - err;
     s = ss;
   }
-  __device__ __forceinline__ LamAcc shfl_xor(int off) const {
-    LamAcc r;
-    r.s = __shfl_xor(s, off, 64);
-    r.c = __shfl_xor(c, off, 64);
-    return r;
-  }
-  __device__ __forceinline__ LamAcc shfl(int lane) const {
-    LamAcc r;
-    r.s = __shfl(s, lane, 64);
-    r.c = __shfl(c, lane, 64);
-    return r;
-  }
   __device__ __forceinline__ uint64_t pack() const {
     return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)__float_as_uint(s);
   }
@@ -162,7 +147,8 @@ struct LamAcc<1> {
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+  // every lane is a valid source of the row rotations, so no old value is needed
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -243,6 +229,34 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   LamAcc<0> a;
   a.s = v;
   return wave_allreduce<0>(a).s;
+}
+
+// NV independent double sums over the lanes t < LANES of a wave (the other
+// lanes must hold 0), interleaved so their latencies overlap; the results are
+// uniform across the wave.  For LANES <= 16 only the first DPP row is read
+// (the rotations leave the row sum in each of its lanes).
+template <int NV, int LANES>
+__device__ __forceinline__ void wave_sums(double (&v)[NV]) {
+#pragma unroll
+  for (int n = 0; n < NV; ++n) v[n] += dpp_f64<kRowRor8>(v[n]);
+#pragma unroll
+  for (int n = 0; n < NV; ++n) v[n] += dpp_f64<kRowRor4>(v[n]);
+#pragma unroll
+  for (int n = 0; n < NV; ++n) v[n] += dpp_f64<kRowRor2>(v[n]);
+#pragma unroll
+  for (int n = 0; n < NV; ++n) v[n] += dpp_f64<kRowRor1>(v[n]);
+#pragma unroll
+  for (int n = 0; n < NV; ++n) {
+    if constexpr (LANES <= 16) {
+      v[n] = readlane_f64(v[n], 0);
+    } else {
+      double r = readlane_f64(v[n], 0);
+      r += readlane_f64(v[n], 16);
+      r += readlane_f64(v[n], 32);
+      r += readlane_f64(v[n], 48);
+      v[n] = r;
+    }
+  }
 }
 
 // Sum of n packed accumulators p[0..n), computed identically by every wave.

@@ -828,7 +828,7 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   A.lam_c = c->p.lam0;
   A.rcd = c->d_rcd;
   A.rcf = c->d_rcf;
-  A.rsf = c->d_rsf;
+  A.rsf = nullptr;  // the fused path serves the accelerated rule only
   A.tsig = c->d_tsig;
   A.nu = c->d_nu;
   A.rh = c->d_rh;

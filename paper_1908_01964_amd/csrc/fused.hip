@@ -3,8 +3,9 @@
 // second-stage iterations (Algorithm 2) in registers, Wiener-filter
 // extraction.  HBM traffic per bin: x (8M bytes) read once; tau^ax, sigma^bx,
 // nu, r^h, r^u (28 bytes) and s_hat (8) written once, plus the caller's
-// copies of r^h, r^u.  The setup of wave 0 overlaps the first x loads of all
-// waves.  One launch per (M, workgroup size, bins per lane) class.
+// copies of r^h, r^u.  Wave 0 issues the setup's loads first; the x loads of
+// the first G bins of every lane follow and overlap the setup.  One launch
+// per (M, workgroup size, bins per lane) class.
 #include "init_common.h"
 #include "resident_loop.h"
 
@@ -25,16 +26,20 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   __shared__ unsigned cflag;
 
   const bool al4 = (M & 1) == 0 && (ri.x_off & 1) == 0;
-  float2 xa[M], xb[M];
-  auto load_bin = [&](int q, float2(&xv)[M]) {
+  // x of the first G bins in flight during the setup (G M complex registers)
+  constexpr int GMAX = NT >= 1024 ? (M <= 4 ? 2 : 1) : (M <= 2 ? 8 : (M <= 4 ? 4 : 2));
+  constexpr int G = BPL < GMAX ? BPL : GMAX;
+  float2 xv[G][M];
+  auto load_bin = [&](int q, float2(&v)[M]) {
     const int j = t + q * NT;
-    if (j < J) load_x<M>(A.x + ri.x_off + (long long)j * M, al4, xv);
+    if (j < J) load_x<M>(A.x + ri.x_off + (long long)j * M, al4, v);
   };
-  load_bin(0, xa);
-  if (BPL > 1) load_bin(1, xb);
+  const SetupIn sin = row_setup_load<M>(A.Rp, A.a, A.b, ri);  // ahead of the x loads
+#pragma unroll
+  for (int q = 0; q < G; ++q) load_bin(q, xv[q]);
   if (t == 0) cflag = 0u;
 
-  if (t < 64) row_setup_wave<M>(A.Rp, A.a, A.b, ri, L);
+  if (t < 64) row_setup_wave<M>(sin, L);
   __syncthreads();
   write_row_constants<M>(L, row, ri, A.rcd, A.rcf, A.rsf, A.lam0, A.lam_c, A.lam, A.status);
   const RowConstF rc = row_const_f<M>(L, ri);
@@ -47,7 +52,7 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   for (int q = 0; q < BPL; ++q) {
     const int j = t + q * NT;
     if (j < J) {
-      precompute_bin<M>(xa, L, inv_taa, ts[q], vnu[q], bad_x);
+      precompute_bin<M>(xv[q % G], L, inv_taa, ts[q], vnu[q], bad_x);
       A.tsig[base + j] = ts[q];
       A.nu[base + j] = vnu[q];
       vrh[q] = A.rh0 ? A.rh0[base + j] : A.rh_c;
@@ -60,11 +65,7 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
       vrh[q] = 1.f;
       vru[q] = 1.f;
     }
-    if (q + 1 < BPL) {
-#pragma unroll
-      for (int m = 0; m < M; ++m) xa[m] = xb[m];
-      if (q + 2 < BPL) load_bin(q + 2, xb);
-    }
+    if (q + G < BPL) load_bin(q + G, xv[q % G]);
   }
   const float lam0 = A.lam0 ? A.lam0[row] : A.lam_c;
   const float lam_fin = resident_iterations<NT, BPL, 0>(ts, vnu, vrh, vru, rc, lam0, row, J, base,

@@ -2,8 +2,8 @@
 // and the initial state, in one launch per microphone count M (one
 // workgroup per chunk of a row).  The arithmetic is in init_common.h.
 //
-// The x loads of each thread's first group of bins are issued before the
-// row setup (wave 0), so their HBM latency overlaps the setup's FP64 work.
+// The setup's loads of a, R', b go first, then the x loads of each thread's
+// first group of bins, so the x latency overlaps the setup's FP64 work.
 // The first chunk of a row writes the row constants, the row's status word
 // and its initial lambda; every chunk writes tau^ax, sigma^bx (float4) and
 // nu (float) for its bins plus their initial r^h, r^u.  Memory-bound: 8M
@@ -35,9 +35,10 @@ __global__ __launch_bounds__(kInitNT) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (jj < ck.len) load_x<M>(A.x + ri.x_off + (long long)(ck.start + jj) * M, al4, xv[q]);
     }
   };
+  const SetupIn sin = row_setup_load<M>(A.Rp, A.a, A.b, ri);  // ahead of the x loads
   load_group(0);
 
-  if (t < 64) row_setup_wave<M>(A.Rp, A.a, A.b, ri, L);
+  if (t < 64) row_setup_wave<M>(sin, L);
   __syncthreads();
   if (ck.start == 0)
     write_row_constants<M>(L, row, ri, A.rcd, A.rcf, A.rsf, A.lam0, A.lam_c, A.lam, A.status);

@@ -27,33 +27,59 @@ namespace rcscm {
 
 template <int M>
 struct SetupLDS {
-  double2 sR[M][M];       // R', then the projected R'
+  double2 sR[M][M];       // projected, Hermitised R'
   double2 sQ[M][M];       // (R')^+
   double2 aug[M][2 * M];  // Gauss-Jordan work array
   double2 sa[M], sb[M], sy[M], sc[M];
-  double taa, sab_re, sab_im, logpdet;
+  double taa, sab_re, sab_im, det_a, shift;
   unsigned flags;
 };
 
-// Row setup by wave 0 (lanes t < 64).  Lane t < M*M owns entry
-// (t / M, t % M); sums over lanes are uniform DPP reductions.
+// The setup's inputs as held by the lanes of wave 0: lane t < M*M holds
+// R'[t / M][t % M] and R'[t % M][t / M], lane t < M holds a[t] and b[t].
+struct SetupIn {
+  double2 r, rt, av, bv;
+};
+
+// Issues the setup's loads (only lanes t < M*M of wave 0 load), so a kernel
+// can put them ahead of its own loads in the memory queue.
 template <int M>
-__device__ void row_setup_wave(const double2* __restrict__ Rp, const double2* __restrict__ a,
-                               const double2* __restrict__ b, const RowInfo& ri,
-                               SetupLDS<M>& L) {
+__device__ __forceinline__ SetupIn row_setup_load(const double2* __restrict__ Rp,
+                                                  const double2* __restrict__ a,
+                                                  const double2* __restrict__ b,
+                                                  const RowInfo& ri) {
+  const int t = threadIdx.x;
+  SetupIn in;
+  in.r = in.rt = in.av = in.bv = make_double2(0.0, 0.0);
+  if (t < M * M) {
+    in.r = Rp[ri.rp_off + t];
+    in.rt = Rp[ri.rp_off + (t % M) * M + t / M];
+  }
+  if (t < M) {
+    in.av = a[ri.a_off + t];
+    in.bv = b[ri.a_off + t];
+  }
+  return in;
+}
+
+// Row setup by wave 0 (lanes t < 64) from its loaded inputs.  Lane t < M*M
+// owns entry (i, j) = (t / M, t % M); sums over lanes are uniform DPP
+// reductions, several at a time.  With y = R' b and e_b = b^H R' b (real part),
+// the projected, Hermitised matrix is
+//   P R' P (Hermitised) = (R' + R'^H)/2 - b y^H - y b^H + e_b b b^H,  P = I - b b^H,
+// computed entrywise without a transpose through LDS.
+template <int M>
+__device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
   const int t = threadIdx.x;
   const int i = t / M, j = t % M;
   const bool ent = t < M * M;
-  double2 r = make_double2(0.0, 0.0), av = r, bv = r;
-  if (ent) r = Rp[ri.rp_off + t];
-  if (t < M) {
-    av = a[ri.a_off + t];
-    bv = b[ri.a_off + t];
-  }
-  const bool fin = zfinite(r) && zfinite(av) && zfinite(bv);
-  const double nbad = wave_sum_d(fin ? 0.0 : 1.0);
-  const double nr2 = wave_sum_d(r.x * r.x + r.y * r.y);
-  const double nb2 = wave_sum_d(bv.x * bv.x + bv.y * bv.y);
+  const double2 r = in.r, av = in.av;
+  double2 bv = in.bv;
+  const bool fin = zfinite(r) && zfinite(in.rt) && zfinite(av) && zfinite(bv);
+  const double2 ab0 = zmulc(av, bv);  // a^H b before normalising b
+  double s1[5] = {fin ? 0.0 : 1.0, r.x * r.x + r.y * r.y, bv.x * bv.x + bv.y * bv.y, ab0.x, ab0.y};
+  wave_sums<5, M * M>(s1);
+  const double nbad = s1[0], nr2 = s1[1], nb2 = s1[2];
   unsigned f = 0u;
   const double nb = sqrt(nb2);
   if (nbad > 0.0) f |= ST_NONFINITE_IN;
@@ -63,7 +89,7 @@ __device__ void row_setup_wave(const double2* __restrict__ Rp, const double2* __
     f |= ST_B_NOT_UNIT;
   const double inb = (nb > 0.0 && nbad == 0.0) ? 1.0 / nb : 0.0;
   bv = make_double2(bv.x * inb, bv.y * inb);
-  if (ent) L.sR[i][j] = r;
+  if (ent) L.aug[i][j] = r;  // R' for the product y = R' b
   if (t < M) {
     L.sa[t] = av;
     L.sb[t] = bv;
@@ -73,56 +99,44 @@ __device__ void row_setup_wave(const double2* __restrict__ Rp, const double2* __
   if (t < M) {
 #pragma unroll
     for (int n = 0; n < M; ++n) {
-      const double2 p = zmul(L.sR[t][n], L.sb[n]);
+      const double2 p = zmul(L.aug[t][n], L.sb[n]);
       y.x += p.x;
       y.y += p.y;
     }
     L.sy[t] = y;
   }
-  const double ny2 = wave_sum_d(y.x * y.x + y.y * y.y);
-  const double be = wave_sum_d(zmulc(bv, y).x);  // b^H R' b
-  if (!(sqrt(ny2) <= 1e-6 * sqrt(nr2))) f |= ST_NOT_NULL;
+  double s2[2] = {y.x * y.x + y.y * y.y, zmulc(bv, y).x};  // ||R' b||^2, b^H R' b
+  wave_sums<2, M>(s2);
+  const double ny2 = s2[0], be = s2[1];
+  if (!(ny2 <= 1e-12 * nr2)) f |= ST_NOT_NULL;  // ||R' b|| <= 1e-6 ||R'||_F
   wave_sync();
-  double2 pr = make_double2(0.0, 0.0);  // P R' P = R' - b y^H - y b^H + (b^H R' b) b b^H
+  double2 rhm = make_double2(0.0, 0.0), bb = rhm;
   if (ent) {
-    const double2 byj = zmul(L.sb[i], zconj(L.sy[j]));
-    const double2 ybj = zmul(L.sy[i], zconj(L.sb[j]));
-    const double2 bbj = zmul(L.sb[i], zconj(L.sb[j]));
-    pr = make_double2(r.x - byj.x - ybj.x + be * bbj.x, r.y - byj.y - ybj.y + be * bbj.y);
-    L.aug[i][j] = pr;
+    const double2 bi = L.sb[i], bj = L.sb[j], yi = L.sy[i], yj = L.sy[j];
+    const double2 byj = zmul(bi, zconj(yj));
+    const double2 ybj = zmul(yi, zconj(bj));
+    bb = zmul(bi, zconj(bj));
+    rhm = make_double2(0.5 * (r.x + in.rt.x) - byj.x - ybj.x + be * bb.x,
+                       0.5 * (r.y - in.rt.y) - byj.y - ybj.y + be * bb.y);
   }
-  wave_sync();
-  double2 rhm = make_double2(0.0, 0.0);  // Hermitised
-  if (ent) {
-    const double2 pt = L.aug[j][i];
-    rhm = make_double2(0.5 * (pr.x + pt.x), 0.5 * (pr.y - pt.y));
-  }
-  const double tr = wave_sum_d((ent && i == j) ? rhm.x : 0.0);
-  const double s = tr > 0.0 ? tr / (double)(M - 1) : 1.0;
-  wave_sync();
+  double s3[1] = {(ent && i == j) ? rhm.x : 0.0};
+  wave_sums<1, M * M>(s3);
+  const double tr = s3[0];
+  const double sh = tr > 0.0 ? tr / (double)(M - 1) : 1.0;
   if (ent) {
     L.sR[i][j] = rhm;
-    const double2 bb = zmul(L.sb[i], zconj(L.sb[j]));
-    L.aug[i][j] = make_double2(rhm.x + s * bb.x, rhm.y + s * bb.y);
+    L.aug[i][j] = make_double2(rhm.x + sh * bb.x, rhm.y + sh * bb.y);
     L.aug[i][M + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   wave_sync();
   double pivprod = 1.0;
   // A = R' + s b b^H has trace tr + s; a pivot below 1e-13 of it means rank(R') < M-1
-  const bool pd = gj_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + s), &pivprod);
-  double2 q = make_double2(0.0, 0.0);  // (R')^+ = A^{-1} - b b^H / s
-  if (ent) {
-    const double2 bb = zmul(L.sb[i], zconj(L.sb[j]));
-    q = make_double2(L.aug[i][M + j].x - bb.x / s, L.aug[i][M + j].y - bb.y / s);
-    L.sQ[i][j] = q;
+  const bool pd = gj_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + sh), &pivprod);
+  if (ent) {  // (R')^+ = A^{-1} - b b^H / s, Hermitised
+    const double ish = 1.0 / sh;
+    const double2 u = L.aug[i][M + j], v = L.aug[j][M + i];
+    L.sQ[i][j] = make_double2(0.5 * (u.x + v.x) - bb.x * ish, 0.5 * (u.y - v.y) - bb.y * ish);
   }
-  wave_sync();
-  if (ent) {
-    const double2 qt = L.sQ[j][i];
-    q = make_double2(0.5 * (q.x + qt.x), 0.5 * (q.y - qt.y));
-  }
-  wave_sync();
-  if (ent) L.sQ[i][j] = q;
   wave_sync();
   double2 cc = make_double2(0.0, 0.0);  // c = (R')^+ a
   if (t < M) {
@@ -134,15 +148,15 @@ __device__ void row_setup_wave(const double2* __restrict__ Rp, const double2* __
     }
     L.sc[t] = cc;
   }
-  const double taa = fmax(wave_sum_d(zmulc(av, cc).x), 0.0);
-  const double2 ab = zmulc(av, bv);
-  const double sabr = wave_sum_d(ab.x), sabi = wave_sum_d(ab.y);
+  double s4[1] = {zmulc(av, cc).x};
+  wave_sums<1, M>(s4);
   if (!pd) f |= ST_NOT_PSD;
   if (t == 0) {
-    L.taa = taa;
-    L.sab_re = sabr;
-    L.sab_im = sabi;
-    L.logpdet = log(pivprod) - log(s);  // log pdet(R') = log det A - log s
+    L.taa = fmax(s4[0], 0.0);
+    L.sab_re = s1[3] * inb;
+    L.sab_im = s1[4] * inb;
+    L.det_a = pivprod;  // det A; log pdet(R') = log det A - log s
+    L.shift = sh;
     L.flags = f;
   }
 }
@@ -162,8 +176,9 @@ __device__ __forceinline__ RowConstF row_const_f(const SetupLDS<M>& L, const Row
 }
 
 // Row constants from the setup (call after the setup and a barrier; threads
-// t < M*M, t < M and t == 0 write their parts).  Also sets the row's initial
-// lambda and its status word.
+// t < M*M, t < M and t == 0 write their parts; rsf may be null when the
+// naive rule is not used).  Also sets the row's initial lambda and its
+// status word.
 template <int M>
 __device__ void write_row_constants(const SetupLDS<M>& L, int row, const RowInfo& ri,
                                     RowConstD* __restrict__ rcd, RowConstF* __restrict__ rcf,
@@ -173,23 +188,28 @@ __device__ void write_row_constants(const SetupLDS<M>& L, int row, const RowInfo
   const int t = threadIdx.x;
   const int i = t / M, j = t % M;
   RowConstD* D = rcd + row;
-  RowSpatialF* S = rsf + row;
   if (t < M * M) {
     D->Q[i * MAXM + j] = L.sQ[i][j];
     D->Rp[i * MAXM + j] = L.sR[i][j];
-    S->Rp[i * MAXM + j] = make_float2((float)L.sR[i][j].x, (float)L.sR[i][j].y);
   }
   if (t < M) {
     D->c[t] = L.sc[t];
     D->b[t] = L.sb[t];
     D->a[t] = L.sa[t];
-    S->a[t] = make_float2((float)L.sa[t].x, (float)L.sa[t].y);
-    S->b[t] = make_float2((float)L.sb[t].x, (float)L.sb[t].y);
+  }
+  if (rsf != nullptr) {  // float spatial model of the naive rule
+    RowSpatialF* S = rsf + row;
+    if (t < M * M) S->Rp[i * MAXM + j] = make_float2((float)L.sR[i][j].x, (float)L.sR[i][j].y);
+    if (t < M) {
+      S->a[t] = make_float2((float)L.sa[t].x, (float)L.sa[t].y);
+      S->b[t] = make_float2((float)L.sb[t].x, (float)L.sb[t].y);
+    }
   }
   if (t == 0) {
     D->t_aa = L.taa;
     D->s_ab = make_double2(L.sab_re, L.sab_im);
-    D->logpdet = L.logpdet;
+    D->det_a = L.det_a;
+    D->shift = L.shift;
     rcf[row] = row_const_f<M>(L, ri);
     const float l = lam0 ? lam0[row] : lam_c;
     lam[row] = l;

@@ -46,7 +46,8 @@ struct RowConstD {
   double2 Rp[MAXM * MAXM]; // projected, Hermitised R' (R' b = 0), row-major
   double2 s_ab;            // a^H b
   double t_aa;             // a^H (R')^+ a
-  double logpdet;          // log of the pseudo-determinant of R'
+  double det_a;            // det(R' + s b b^H); pdet(R') = det_a / s
+  double shift;            // s = tr(R') / (M - 1)
 };
 
 // Float spatial model for the naive rule: a, b and the projected R'.

@@ -3,6 +3,8 @@
 // single-launch kernel.  Per iteration: phase A over the lane's bins, the
 // lambda frame sum (DPP within each wave, one LDS slot per wave, one barrier;
 // the slots are double-buffered so no second barrier is needed), phase B.
+// Under the F64 policy a lane adds its <= BPL terms in float and the lanes
+// and waves are combined in double.
 #pragma once
 
 #include "accel_common.h"
@@ -22,6 +24,9 @@ __device__ __forceinline__ float resident_iterations(
   const int t = threadIdx.x;
   const int wave = t >> 6;
   const double invJ = 1.0 / (double)J;
+  float nuM[BPL];  // nu / M, the form phase B takes
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) nuM[q] = vnu[q] * rc.invM;
   LamTerms Lt = lam_terms(rc, lam_t);
   for (int k = 0; k < K; ++k) {
     if (ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
@@ -37,19 +42,25 @@ __device__ __forceinline__ float resident_iterations(
     }
     LamAcc<LS> acc;
     PhaseA A[BPL];
+    float tsum = 0.0f;  // F64 policy: the lane's <= BPL terms in float, lanes in double
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       A[q] = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
-      if (t + q * NT < J) acc.add(A[q].t);
+      const bool in = t + q * NT < J;
+      if constexpr (LS == 0)
+        tsum += in ? A[q].t : 0.0f;
+      else if (in)
+        acc.add(A[q].t);
       vrh[q] = A[q].rh_new;
     }
+    if constexpr (LS == 0) acc.s = (double)tsum;
     acc = wave_allreduce<LS>(acc);
     if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
     __syncthreads();
     const float lam_n = slots_sum<LS, NW>(red[k & 1]).mean(invJ);
     const LamTerms Ln = lam_terms(rc, lam_n);
 #pragma unroll
-    for (int q = 0; q < BPL; ++q) vru[q] = phase_b(ts[q], vnu[q], A[q], rc, Ln);
+    for (int q = 0; q < BPL; ++q) vru[q] = phase_b(ts[q], nuM[q], A[q], rc, Ln);
     lam_t = lam_n;
     Lt = Ln;
   }

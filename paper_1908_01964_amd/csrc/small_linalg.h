@@ -24,11 +24,20 @@ __device__ __forceinline__ double2 zmulc(double2 a, double2 b) {  // conj(a) b
 __device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ bool zfinite(double2 v) { return isfinite(v.x) && isfinite(v.y); }
 
+// 1/p in FP64 for p > 0: the hardware estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - p r), each of which doubles the number of correct bits.
+__device__ __forceinline__ double rcp_f64_nr(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return fma(r, fma(-p, r, 1.0), r);
+}
+
 // In-place inverse of a Hermitian positive-definite M x M matrix by
 // Gauss-Jordan elimination without pivoting (stable for HPD matrices: every
 // pivot is a positive Schur-complement diagonal).  aug is LDS [M][2M]:
 // [A | I] on entry, [I | A^{-1}] on exit.  Lane t < M*M of wave 0 updates
-// entry (t / M, t % M) of both halves in each of the M elimination steps.
+// entry (t / M, t % M) of both halves in each of the M elimination steps;
+// every step reads all it needs in one batch of LDS loads, then writes.
 // Returns false (and continues with a clamped pivot) when a pivot is <= tol;
 // *pivprod receives the product of the pivots (= det A).
 template <int M>
@@ -41,19 +50,21 @@ __device__ bool gj_inverse_hpd_wave(double2 (*aug)[2 * M], double tol, double* p
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     double p = aug[k][k].x;
+    double2 f = make_double2(0.0, 0.0), r1 = f, r2 = f, a1 = f, a2 = f;
+    if (on) {
+      f = aug[i][k];
+      r1 = aug[k][j];
+      r2 = aug[k][M + j];
+      a1 = aug[i][j];
+      a2 = aug[i][M + j];
+    }
     if (!(p > tol)) {
       ok = false;
       p = fmax(tol, 1e-300);
     }
     prod *= p;
-    const double ip = 1.0 / p;
-    double2 f = make_double2(0.0, 0.0), r1 = f, r2 = f;
-    if (on) {
-      f = aug[i][k];
-      r1 = aug[k][j];
-      r2 = aug[k][M + j];
-    }
-    wave_sync();
+    const double ip = rcp_f64_nr(p);
+    wave_sync();  // every lane's reads of this step precede any write
     if (on) {
       const double2 n1 = make_double2(r1.x * ip, r1.y * ip);
       const double2 n2 = make_double2(r2.x * ip, r2.y * ip);
@@ -62,8 +73,8 @@ __device__ bool gj_inverse_hpd_wave(double2 (*aug)[2 * M], double tol, double* p
         aug[k][M + j] = n2;
       } else {
         const double2 d1 = zmul(f, n1), d2 = zmul(f, n2);
-        aug[i][j] = make_double2(aug[i][j].x - d1.x, aug[i][j].y - d1.y);
-        aug[i][M + j] = make_double2(aug[i][M + j].x - d2.x, aug[i][M + j].y - d2.y);
+        aug[i][j] = make_double2(a1.x - d1.x, a1.y - d1.y);
+        aug[i][M + j] = make_double2(a2.x - d2.x, a2.y - d2.y);
       }
     }
     wave_sync();
