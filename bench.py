@@ -179,17 +179,16 @@ def time_run(ctx, inputs, out, K, steps, warmup, torch):
     for _ in range(warmup):
         ctx.run(x, a, Rp, b, K, out=out)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record()
-    for s in range(steps):
+    e0.record()
+    for _ in range(steps):
         ctx.run(x, a, Rp, b, K, out=out)
-        ev[s + 1].record()
+    e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = [ev[s].elapsed_time(ev[s + 1]) * 1e3 for s in range(steps)]  # microseconds
-    return wall, sum(per) / steps
+    return wall, e0.elapsed_time(e1) * 1e3 / steps  # average launch in microseconds
 
 
 def time_backproject(I, J, M, K, steps, torch):

@@ -64,6 +64,8 @@ struct rcscm_ctx {
   std::vector<ResClass> first_classes;  // FIRST rule: nt field holds M
   struct FusedClass {
     int M, nt, bpl, count, offset;
+    bool linear;  // consecutive rows of one utterance (offsets linear in the row index)
+    int row0;     // first row of the class
   };
   std::vector<FusedClass> fused_classes;  // rcscm_run (empty: not available)
 
@@ -381,12 +383,21 @@ static rcscm_status build_tables(rcscm_ctx* c) {
     }
     if (ok)
       for (auto& kv : cls) {
-        c->fused_classes.push_back(rcscm_ctx::FusedClass{std::get<0>(kv.first),
-                                                         std::get<1>(kv.first),
-                                                         std::get<2>(kv.first),
-                                                         (int)kv.second.size(),
-                                                         (int)row_list.size()});
-        row_list.insert(row_list.end(), kv.second.begin(), kv.second.end());
+        const std::vector<int>& rl = kv.second;
+        bool linear = true;
+        const RowInfo& r0 = c->h_rows[rl[0]];
+        for (size_t k = 1; k < rl.size() && linear; ++k) {
+          const RowInfo& rk = c->h_rows[rl[k]];
+          const long long kk = (long long)k;
+          linear = rl[k] == rl[0] + (int)k && rk.utt == r0.utt && rk.J == r0.J &&
+                   rk.M == r0.M && rk.x_off == r0.x_off + kk * r0.J * r0.M &&
+                   rk.bin_off == r0.bin_off + kk * r0.J && rk.a_off == r0.a_off + kk * r0.M &&
+                   rk.rp_off == r0.rp_off + kk * r0.M * r0.M;
+        }
+        c->fused_classes.push_back(rcscm_ctx::FusedClass{
+            std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), (int)rl.size(),
+            (int)row_list.size(), linear, rl[0]});
+        row_list.insert(row_list.end(), rl.begin(), rl.end());
       }
   }
   if (row_list.empty()) row_list.push_back(0);
@@ -845,6 +856,17 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   c->chunk_status_valid = false;  // the fused kernel reports through status[row] only
   for (const auto& cl : c->fused_classes) {
     A.row_list = c->d_row_list + cl.offset;
+    A.lin = 0;
+    if (cl.linear) {
+      const RowInfo& r0 = c->h_rows[cl.row0];
+      A.lin = 1;
+      A.lin_row0 = cl.row0;
+      A.lin_J = r0.J;
+      A.lin_x0 = r0.x_off;
+      A.lin_bin0 = r0.bin_off;
+      A.lin_a0 = r0.a_off;
+      A.lin_rp0 = r0.rp_off;
+    }
     launch_fused(c->stream, cl.M, cl.nt, cl.bpl, cl.count, A);
     RCSCM_HIP(c, hipGetLastError());
   }

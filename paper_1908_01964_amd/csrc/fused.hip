@@ -16,8 +16,21 @@ namespace {
 template <int M, int NT, int BPL>
 __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   constexpr int NW = NT / 64;
-  const int row = A.row_list[blockIdx.x];
-  const RowInfo ri = A.rows[row];
+  int row;
+  RowInfo ri;
+  if (A.lin) {  // no dependent loads before the setup's loads
+    const long long b = blockIdx.x;
+    row = A.lin_row0 + (int)b;
+    ri.J = A.lin_J;
+    ri.M = M;
+    ri.x_off = A.lin_x0 + b * A.lin_J * M;
+    ri.bin_off = A.lin_bin0 + b * A.lin_J;
+    ri.a_off = A.lin_a0 + b * M;
+    ri.rp_off = A.lin_rp0 + b * M * M;
+  } else {
+    row = A.row_list[blockIdx.x];
+    ri = A.rows[row];
+  }
   const int J = ri.J;
   const long long base = ri.bin_off;
   const int t = threadIdx.x;
@@ -41,9 +54,9 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
 
   if (t < 64) row_setup_wave<M>(sin, L);
   __syncthreads();
-  write_row_constants<M>(L, row, ri, A.rcd, A.rcf, A.rsf, A.lam0, A.lam_c, A.lam, A.status);
+  write_row_constants<M, NT>(L, row, ri, A.rcd, A.rcf, A.rsf, A.lam0, A.lam_c, A.lam, A.status);
   const RowConstF rc = row_const_f<M>(L, ri);
-  const double inv_taa = L.taa > 0.0 ? 1.0 / L.taa : 0.0;
+  const double inv_taa = L.inv_taa;
 
   float4 ts[BPL];
   float vnu[BPL], vrh[BPL], vru[BPL];

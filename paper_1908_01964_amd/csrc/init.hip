@@ -41,9 +41,10 @@ __global__ __launch_bounds__(kInitNT) __attribute__((amdgpu_waves_per_eu(4))) vo
   if (t < 64) row_setup_wave<M>(sin, L);
   __syncthreads();
   if (ck.start == 0)
-    write_row_constants<M>(L, row, ri, A.rcd, A.rcf, A.rsf, A.lam0, A.lam_c, A.lam, A.status);
+    write_row_constants<M, kInitNT>(L, row, ri, A.rcd, A.rcf, A.rsf, A.lam0, A.lam_c, A.lam,
+                                    A.status);
 
-  const double inv_taa = L.taa > 0.0 ? 1.0 / L.taa : 0.0;
+  const double inv_taa = L.inv_taa;
   bool bad_x = false, bad_state = false;
   for (int g0 = 0; g0 < ck.len; g0 += G * kInitNT) {
     if (g0 > 0) load_group(g0);

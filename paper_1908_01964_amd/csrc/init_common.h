@@ -31,7 +31,7 @@ struct SetupLDS {
   double2 sQ[M][M];       // (R')^+
   double2 aug[M][2 * M];  // Gauss-Jordan work array
   double2 sa[M], sb[M], sy[M], sc[M];
-  double taa, sab_re, sab_im, det_a, shift;
+  double taa, inv_taa, sab_re, sab_im, det_a, shift;
   unsigned flags;
 };
 
@@ -152,7 +152,9 @@ __device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
   wave_sums<1, M>(s4);
   if (!pd) f |= ST_NOT_PSD;
   if (t == 0) {
-    L.taa = fmax(s4[0], 0.0);
+    const double taa = fmax(s4[0], 0.0);
+    L.taa = taa;
+    L.inv_taa = taa > 0.0 ? rcp_f64_nr(taa) : 0.0;
     L.sab_re = s1[3] * inb;
     L.sab_im = s1[4] * inb;
     L.det_a = pivprod;  // det A; log pdet(R') = log det A - log s
@@ -168,44 +170,48 @@ __device__ __forceinline__ RowConstF row_const_f(const SetupLDS<M>& L, const Row
   F.sab_re = (float)L.sab_re;
   F.sab_im = (float)L.sab_im;
   F.sab2 = (float)(L.sab_re * L.sab_re + L.sab_im * L.sab_im);
-  F.inv_t_aa = L.taa > 0.0 ? (float)(1.0 / L.taa) : 0.0f;
+  F.inv_t_aa = (float)L.inv_taa;
   F.invM = (float)(1.0 / (double)M);
-  F.invJ = (float)(1.0 / (double)ri.J);
+  F.invJ = 1.0f / (float)ri.J;
   F.pad = 0.0f;
   return F;
 }
 
-// Row constants from the setup (call after the setup and a barrier; threads
-// t < M*M, t < M and t == 0 write their parts; rsf may be null when the
-// naive rule is not used).  Also sets the row's initial lambda and its
-// status word.
-template <int M>
+// Row constants from the setup (call after the setup and a barrier).  The
+// stores are spread over the threads of a workgroup of NT >= 256 lanes, one
+// or two per thread: Q by threads [0, M*M), R' by [64, 64 + M*M), c, b, a by
+// [128, 128 + M), [160, ...), [192, ...), the scalars by thread 224.  rsf
+// (the float model of the naive rule) may be null.  Also sets the row's
+// initial lambda and its status word.
+template <int M, int NT>
 __device__ void write_row_constants(const SetupLDS<M>& L, int row, const RowInfo& ri,
                                     RowConstD* __restrict__ rcd, RowConstF* __restrict__ rcf,
                                     RowSpatialF* __restrict__ rsf, const float* __restrict__ lam0,
                                     float lam_c, float* __restrict__ lam,
                                     unsigned* __restrict__ status) {
+  static_assert(NT >= 256 && M * M <= 64 && M <= 32, "thread map of the row constants");
   const int t = threadIdx.x;
-  const int i = t / M, j = t % M;
   RowConstD* D = rcd + row;
+  RowSpatialF* S = rsf != nullptr ? rsf + row : nullptr;
   if (t < M * M) {
+    const int i = t / M, j = t % M;
     D->Q[i * MAXM + j] = L.sQ[i][j];
-    D->Rp[i * MAXM + j] = L.sR[i][j];
-  }
-  if (t < M) {
-    D->c[t] = L.sc[t];
-    D->b[t] = L.sb[t];
-    D->a[t] = L.sa[t];
-  }
-  if (rsf != nullptr) {  // float spatial model of the naive rule
-    RowSpatialF* S = rsf + row;
-    if (t < M * M) S->Rp[i * MAXM + j] = make_float2((float)L.sR[i][j].x, (float)L.sR[i][j].y);
-    if (t < M) {
-      S->a[t] = make_float2((float)L.sa[t].x, (float)L.sa[t].y);
-      S->b[t] = make_float2((float)L.sb[t].x, (float)L.sb[t].y);
-    }
-  }
-  if (t == 0) {
+  } else if (t >= 64 && t < 64 + M * M) {
+    const int i = (t - 64) / M, j = (t - 64) % M;
+    const double2 r = L.sR[i][j];
+    D->Rp[i * MAXM + j] = r;
+    if (S) S->Rp[i * MAXM + j] = make_float2((float)r.x, (float)r.y);
+  } else if (t >= 128 && t < 128 + M) {
+    D->c[t - 128] = L.sc[t - 128];
+  } else if (t >= 160 && t < 160 + M) {
+    const double2 v = L.sb[t - 160];
+    D->b[t - 160] = v;
+    if (S) S->b[t - 160] = make_float2((float)v.x, (float)v.y);
+  } else if (t >= 192 && t < 192 + M) {
+    const double2 v = L.sa[t - 192];
+    D->a[t - 192] = v;
+    if (S) S->a[t - 192] = make_float2((float)v.x, (float)v.y);
+  } else if (t == 224) {
     D->t_aa = L.taa;
     D->s_ab = make_double2(L.sab_re, L.sab_im);
     D->det_a = L.det_a;

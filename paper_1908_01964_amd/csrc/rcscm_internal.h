@@ -101,6 +101,11 @@ void launch_init(hipStream_t s, int M, int nchunks, const InitArgs& args);
 struct FusedArgs {
   const int* row_list;
   const RowInfo* rows;
+  // Linear launch: block b serves row lin_row0 + b, whose J is lin_J and
+  // whose offsets are the base offsets plus b times the per-row strides
+  // (rows of one utterance); the row table is then not read.
+  int lin, lin_row0, lin_J;
+  long long lin_x0, lin_bin0, lin_a0, lin_rp0;
   const float2* x;
   const double2* a;
   const double2* Rp;
