@@ -29,9 +29,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic cost of one accelerated bin-update (accel_common.h, counted with
-# FMA = 2 flops, reciprocal = 1): phase A 39 flops, phase B 14 flops.
-FLOPS_PER_UPDATE = 53
+# Arithmetic of one accelerated bin-update in the form the kernels evaluate it
+# (accel_common.h; FMA = 2 flops, multiply, add and reciprocal = 1): phase A 36
+# (rho~ax 8, gamma~ 4, w and gamma~ r~u 3, r^h 6, e 8, |e|^2 3, t 4), the frame
+# sum 1, phase B 13.
+FLOPS_PER_UPDATE = 50
 # Algorithmic HBM bytes of one resident launch per bin (whole K loop):
 # read tau^ax, sigma^bx (16), nu (4), r^h, r^u (8); write r^h, r^u (8).
 RESIDENT_BYTES_PER_BIN = 36

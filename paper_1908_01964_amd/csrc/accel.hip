@@ -5,9 +5,9 @@
 // RESIDENT: one workgroup per (utterance, frequency) row.  Each lane holds
 //   BPL bins (frames j = lane + q*NT) of the row in registers - tau^ax,
 //   sigma^bx, nu, r^h, r^u - for all K iterations.  Per iteration: phase A
-//   over the lane's bins, the lambda frame sum (wave butterfly, then one LDS
-//   slot per wave, one barrier), phase B.  HBM traffic: 28 bytes read and
-//   8 bytes written per bin for the whole K loop.
+//   over the lane's bins, the lambda frame sum (DPP rotations within each
+//   wave, then one LDS slot per wave, one barrier), phase B.  HBM traffic:
+//   28 bytes read and 8 bytes written per bin for the whole K loop.
 //
 // STREAM: rows are cut into chunks; launch k (k = 1..K+1) finishes iteration
 //   k-1 and starts iteration k.  Finishing iteration k-1 needs lambda_{k-1},
