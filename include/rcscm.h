@@ -164,7 +164,10 @@ rcscm_status rcscm_extract(rcscm_ctx* ctx, float* rh, float* ru, float* lam, voi
  * lambda sum and no checkpoints, each row runs its whole path - FP64 setup,
  * FP64 precomputation, K iterations, extraction - in one workgroup of one
  * launch per (M, workgroup size) class, reading x once and writing the
- * results once; otherwise the three calls are made in turn.  Leaves the
+ * results once; otherwise the three calls are made in turn.  With several
+ * classes the launches are spread over up to three library-owned
+ * non-blocking streams that fork from and join back into the context's
+ * stream, so completion is still ordered on that stream.  Leaves the
  * context in the same state as the three calls (iterate/extract/objective
  * may follow).  Asynchronous. */
 rcscm_status rcscm_run(rcscm_ctx* ctx, const void* x, const void* a, const void* Rp,

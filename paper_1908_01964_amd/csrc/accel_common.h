@@ -25,6 +25,13 @@ namespace rcscm {
 
 __device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// 1/v for the per-iteration lambda: the hardware reciprocal refined by one
+// Newton-Raphson step r <- r + r (1 - v r) (about 0.5 ulp for normal v > 0).
+__device__ __forceinline__ float frcp_nr(float v) {
+  const float r = __builtin_amdgcn_rcpf(v);
+  return fmaf(r, fmaf(-v, r, 1.0f), r);
+}
+
 // Per-row quantities that depend on one value of lambda.  The *M members are
 // the same quantities divided by M, used by phase B.
 struct LamTerms {
@@ -39,7 +46,7 @@ struct LamTerms {
 
 __device__ __forceinline__ LamTerms lam_terms(const RowConstF& rc, float lam) {
   LamTerms L;
-  L.il = 1.0f / lam;
+  L.il = frcp_nr(lam);
   L.rho_aa = fmaf(rc.sab2, L.il, rc.t_aa);
   L.sp_re = rc.sab_re * L.il;
   L.sp_im = rc.sab_im * L.il;

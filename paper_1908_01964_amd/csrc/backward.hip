@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NT) void backward_kernel(
   float lam_bar;
   {
     const float lam = lam_fin[row];
-    const float il = 1.0f / lam;
+    const float il = frcp_nr(lam);
     const float A = fmaf(S2, il, taa);
     double c = 0.0;
 #pragma unroll
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(NT) void backward_kernel(
   for (int k = K - 1; k >= 0; --k) {
     const float lam = ck_lam[(long long)k * sr + row];
     const float lam_n = (k + 1 < K) ? ck_lam[(long long)(k + 1) * sr + row] : lam_fin[row];
-    const float il = 1.0f / lam, il_n = 1.0f / lam_n;
+    const float il = frcp_nr(lam), il_n = frcp_nr(lam_n);
     const float A = fmaf(S2, il, taa), A_n = fmaf(S2, il_n, taa);
     float vh[BPL], vu[BPL];
     double c1 = 0.0;

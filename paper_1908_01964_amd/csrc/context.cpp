@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <tuple>
@@ -106,6 +107,12 @@ struct rcscm_ctx {
   std::string err;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
+  // rcscm_run with several workgroup classes: the class launches are forked
+  // over auxiliary streams (non-blocking, default priority) and joined back.
+  int device = 0;
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
 
   rcscm_status fail(rcscm_status s, const std::string& m) {
     err = m;
@@ -503,6 +510,7 @@ static rcscm_status create_impl(rcscm_ctx** out, int U, int I, const int* J, con
   c->M.assign(M, M + U);
   c->p = p;
   c->stream = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetDevice(&c->device);
   s = build_tables(c);
   if (s == RCSCM_OK) s = alloc_workspace(c);
   if (s != RCSCM_OK) {
@@ -811,6 +819,25 @@ rcscm_status rcscm_backproject(rcscm_ctx* c, const void* x, const void* W, const
   return RCSCM_OK;
 }
 
+// Creates the auxiliary streams and events of a multi-class rcscm_run (once).
+static rcscm_status ensure_aux(rcscm_ctx* c, int n) {
+  if ((int)c->aux.size() >= n) return RCSCM_OK;
+  int cur = 0;
+  RCSCM_HIP(c, hipGetDevice(&cur));
+  if (cur != c->device) RCSCM_HIP(c, hipSetDevice(c->device));
+  if (!c->ev_fork) RCSCM_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  while ((int)c->aux.size() < n) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    RCSCM_HIP(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    c->aux.push_back(st);
+    RCSCM_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    c->ev_join.push_back(ev);
+  }
+  if (cur != c->device) RCSCM_HIP(c, hipSetDevice(cur));
+  return RCSCM_OK;
+}
+
 rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* Rp, const void* b,
                        const float* rh0, const float* ru0, const float* lam0, int K, float* rh,
                        float* ru, float* lam, void* s_hat) {
@@ -854,7 +881,26 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   A.beta_a2 = (float)(c->p.beta / (c->p.alpha + 2.0));
   A.K = K;
   c->chunk_status_valid = false;  // the fused kernel reports through status[row] only
-  for (const auto& cl : c->fused_classes) {
+  // Largest class first on the context's stream; the others go round-robin to
+  // up to three auxiliary streams, so the tail of one class launch overlaps
+  // the next class instead of leaving CUs idle.
+  const int ncls = (int)c->fused_classes.size();
+  std::vector<int> order(ncls);
+  for (int k = 0; k < ncls; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int u, int v) {
+    const auto& a = c->fused_classes[u];
+    const auto& b = c->fused_classes[v];
+    return (long long)a.count * a.nt * a.bpl > (long long)b.count * b.nt * b.bpl;
+  });
+  const int naux = std::min(3, ncls - 1);
+  if (naux > 0) {
+    RCSCM_TRY(ensure_aux(c, naux));
+    RCSCM_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+    for (int k = 0; k < naux; ++k) RCSCM_HIP(c, hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
+  }
+  for (int oi = 0; oi < ncls; ++oi) {
+    const auto& cl = c->fused_classes[order[oi]];
+    hipStream_t st = oi == 0 ? c->stream : c->aux[(oi - 1) % naux];
     A.row_list = c->d_row_list + cl.offset;
     A.lin = 0;
     if (cl.linear) {
@@ -867,8 +913,12 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
       A.lin_a0 = r0.a_off;
       A.lin_rp0 = r0.rp_off;
     }
-    launch_fused(c->stream, cl.M, cl.nt, cl.bpl, cl.count, A);
+    launch_fused(st, cl.M, cl.nt, cl.bpl, cl.count, A);
     RCSCM_HIP(c, hipGetLastError());
+  }
+  for (int k = 0; k < naux; ++k) {
+    RCSCM_HIP(c, hipEventRecord(c->ev_join[k], c->aux[k]));
+    RCSCM_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
   }
   c->x_borrowed = static_cast<const float2*>(x);
   c->inited = true;
@@ -887,6 +937,12 @@ rcscm_status rcscm_get_schedule(const rcscm_ctx* c, int* schedule, int* block, i
 void rcscm_destroy(rcscm_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  for (hipStream_t st : c->aux) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (hipEvent_t ev : c->ev_join) (void)hipEventDestroy(ev);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
   delete c;
