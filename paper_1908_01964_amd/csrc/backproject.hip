@@ -76,34 +76,46 @@ __global__ __launch_bounds__(kBpNT) void bp_power_kernel(const ChunkInfo* __rest
   }
 }
 
-// Smallest eigenvalue of a Hermitian n x n matrix (n <= 7) held in LDS, by
-// cyclic complex Jacobi rotations; one lane.
-__device__ double jacobi_min_eig(double2 (*H)[MAXM], int n) {
+// Smallest eigenvalue of a Hermitian N x N matrix (N <= 7) by cyclic complex
+// Jacobi rotations, run by one lane on a copy held in registers (every index
+// is a compile-time constant).  Each rotation first makes H[p][q] real with a
+// phase on row/column q, then applies the real rotation that zeroes it.
+template <int N>
+__device__ double jacobi_min_eig(const double2 (*G)[MAXM]) {
+  double2 H[N][N];
+#pragma unroll
+  for (int p = 0; p < N; ++p)
+#pragma unroll
+    for (int q = 0; q < N; ++q) H[p][q] = G[p][q];
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int p = 0; p < n; ++p) {
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
       dia += H[p][p].x * H[p][p].x;
-      for (int q = p + 1; q < n; ++q) off += H[p][q].x * H[p][q].x + H[p][q].y * H[p][q].y;
+#pragma unroll
+      for (int q = p + 1; q < N; ++q) off += H[p][q].x * H[p][q].x + H[p][q].y * H[p][q].y;
     }
     if (off <= 1e-30 * dia) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
+#pragma unroll
+    for (int p = 0; p < N; ++p)
+#pragma unroll
+      for (int q = p + 1; q < N; ++q) {
         const double2 apq = H[p][q];
         const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
         if (mag < 1e-300) continue;
-        // phase: make H[p][q] real (column q times conj(ph), row q times ph)
         const double2 ph = make_double2(apq.x / mag, apq.y / mag);
-        for (int r = 0; r < n; ++r) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
           if (r == q) continue;
           H[r][q] = zmul(H[r][q], zconj(ph));
           H[q][r] = zconj(H[r][q]);
         }
-        // real rotation zeroing the (p, q) entry
         const double a = H[p][p].x, bq = H[q][q].x;
         const double th = (bq - a) / (2.0 * mag);
         const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
         const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
-        for (int r = 0; r < n; ++r) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
           if (r == p || r == q) continue;
           const double2 rp = H[r][p], rq = H[r][q];
           const double2 np_ = make_double2(cs * rp.x - sn * rq.x, cs * rp.y - sn * rq.y);
@@ -120,7 +132,8 @@ __device__ double jacobi_min_eig(double2 (*H)[MAXM], int n) {
       }
   }
   double mn = H[0][0].x;
-  for (int p = 1; p < n; ++p) mn = fmin(mn, H[p][p].x);
+#pragma unroll
+  for (int p = 1; p < N; ++p) mn = fmin(mn, H[p][p].x);
   return mn;
 }
 
@@ -247,7 +260,7 @@ __global__ __launch_bounds__(64) void bp_row_kernel(const int* __restrict__ row_
       G[k][l] = make_double2(w * s.x, w * s.y);
     }
     wave_sync();
-    if (t == 0) lam0_out[row] = (float)jacobi_min_eig(G, n1);
+    if (t == 0) lam0_out[row] = (float)jacobi_min_eig<M - 1>(G);
   }
   if (t == 0 && sflag) atomicOr(status + row, sflag);
 }

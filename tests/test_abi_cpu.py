@@ -80,6 +80,10 @@ def test_null_context_calls():
     assert L.rcscm_backward(None, None, None, None, None, None) == R.EINVAL
     v = ctypes.c_double()
     assert L.rcscm_objective(None, ctypes.byref(v)) == R.EINVAL
+    assert L.rcscm_run(None, None, None, None, None, None, None, None, 1, None, None, None,
+                       None) == R.EINVAL
+    tg = (ctypes.c_int * 1)(0)
+    assert L.rcscm_backproject(None, None, None, tg, None, None, None, None, None) == R.EINVAL
     L.rcscm_destroy(None)
 
 
