@@ -84,8 +84,11 @@ typedef enum { RCSCM_RULE_NAIVE = 0, RCSCM_RULE_ACCEL = 1, RCSCM_RULE_FIRST = 2 
 typedef enum { RCSCM_SCHED_AUTO = 0, RCSCM_SCHED_STREAM = 1, RCSCM_SCHED_RESIDENT = 2 } rcscm_sched;
 
 /* How the per-frequency sum over frames for lambda (eqs. (18), (43), (55)) is
- * accumulated.  F64: per-lane and cross-lane sums in double.  KAHAN32:
- * Kahan-compensated float per lane, then a compensated (TwoSum) float tree. */
+ * accumulated by the accelerated rule.  F64: each lane adds its (at most 16)
+ * terms in float, lanes and waves are combined in double in a fixed order
+ * (relative error about 1e-6 at worst; reproducible run to run).  KAHAN32:
+ * Kahan-compensated float per lane, then a compensated (TwoSum) float tree.
+ * The naive and first-stage rules sum in double throughout. */
 typedef enum { RCSCM_LAMSUM_F64 = 0, RCSCM_LAMSUM_KAHAN32 = 1 } rcscm_lamsum;
 
 #define RCSCM_FLAG_GRAPH       1u  /* capture the STREAM K loop in a hipGraph      */
@@ -219,7 +222,10 @@ rcscm_status rcscm_backward(rcscm_ctx* ctx, const void* x, const void* grad_s_ha
  * x as in rcscm_init.  All arithmetic is FP64 on the device.  Asynchronous
  * (after a small host-to-device copy of the target indices).  Errors: EINVAL
  * (NULL pointers, target out of range); a singular W is reported as ENOTPSD
- * by the next rcscm_sync.  The initialisation of r^h from the NMF factors of
+ * by the next rcscm_sync (rcscm_init and rcscm_run reset the per-row status
+ * and judge the a, R', b they receive by their own checks, so call
+ * rcscm_sync in between to see this error).  The initialisation of r^h from
+ * the NMF factors of
  * ILRMA (eq. (21)) is the caller's (pass it to rcscm_init as rh0). */
 rcscm_status rcscm_backproject(rcscm_ctx* ctx, const void* x, const void* W, const int* target,
                                void* a, void* Rp, void* b, float* ru0, float* lam0);

@@ -99,10 +99,12 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   if (t == 0) {
     A.lam[row] = lam_fin;
     if (A.lam_out) A.lam_out[row] = lam_fin;
-    if (!(lam_fin > 0.0f) || !isfinite(lam_fin)) atomicOr(A.status + row, ST_LAM_NONPOS);
+    if (!(lam_fin > 0.0f) || !isfinite(lam_fin)) atomicOr(&cflag, ST_LAM_NONPOS);
   }
   if (bad_x) atomicOr(&cflag, ST_NONFINITE_IN);
   if (bad_state) atomicOr(&cflag, ST_NONFINITE_STATE);
+  // the status word was stored by write_row_constants; OR the new bits in only
+  // after a barrier (with K = 0 the iterations contain none)
   __syncthreads();
   if (t == 0 && cflag) atomicOr(A.status + row, cflag);
 }

@@ -15,8 +15,9 @@ def nrel(est, ref):
     return float(np.linalg.norm(est - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
-def gpu_run(problems, K, init_arrays=None, **params):
-    """Runs init + iterate(K) + extract on the GPU; returns per-utterance numpy dicts."""
+def gpu_run(problems, K, init_arrays=None, fused=False, **params):
+    """Runs init + iterate(K) + extract on the GPU (fused=True: the single call rcscm_run);
+    returns per-utterance numpy dicts."""
     import torch
 
     from paper_1908_01964_amd import Context, to_device
@@ -30,9 +31,12 @@ def gpu_run(problems, K, init_arrays=None, **params):
     if init_arrays is not None:
         kw = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32).ravel()).cuda()
               for k, v in init_arrays.items()}
-    ctx.init(x, a, Rp, b, **kw)
-    ctx.iterate(K)
-    out = ctx.extract()
+    if fused:
+        out = ctx.run(x, a, Rp, b, K, **kw)
+    else:
+        ctx.init(x, a, Rp, b, **kw)
+        ctx.iterate(K)
+        out = ctx.extract()
     ctx.sync()
     res = {k: v.cpu().numpy() for k, v in out.items()}
     ctx.close()

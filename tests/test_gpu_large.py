@@ -24,11 +24,14 @@ def _sample_rows(Js, n=16, seed=0):
     return list(zip(us.tolist(), iis.tolist()))
 
 
-@pytest.mark.parametrize("schedule", ["resident", "stream"])
+@pytest.mark.parametrize("schedule", ["resident", "stream", "fused"])
 def test_config2_full_batch_sampled_rows(batch, schedule):
     Js, Ms, probs = batch
     K = 20
-    outs = gpu_run(probs, K, schedule=schedule)
+    if schedule == "fused":  # rcscm_run: one launch per class, classes spread over streams
+        outs = gpu_run(probs, K, fused=True)
+    else:
+        outs = gpu_run(probs, K, schedule=schedule)
     got = {k: [] for k in ("rh", "ru", "lam", "s_hat")}
     ref = {k: [] for k in got}
     for u, i in _sample_rows(Js):
@@ -62,8 +65,11 @@ def test_config4_full_size_subsample():
     sel = np.round(np.linspace(0, p.I - 1, 64)).astype(int)
     sub = config(4, freqs=sel)
     ref = oracle_accel(sub, K)
-    for schedule in ("resident", "stream"):
-        out = gpu_run(p, K, schedule=schedule)[0]
+    for schedule in ("resident", "stream", "fused"):
+        if schedule == "fused":  # the bench step: accel_fused_kernel<8, 1024, 8>
+            out = gpu_run(p, K, fused=True)[0]
+        else:
+            out = gpu_run(p, K, schedule=schedule)[0]
         got = {k: v[sel] for k, v in out.items()}
         e = assert_close(got, ref, what=f"config 4 {schedule}")
         print("config4", schedule, e)

@@ -112,7 +112,8 @@ def test_graph_equals_eager(c0):
     cg.close()
 
 
-def test_explicit_initial_state():
+@pytest.mark.parametrize("fused", [False, True])
+def test_explicit_initial_state(fused):
     p = make_problem(4, 5, 200, config=430)
     rng = np.random.default_rng(1)
     rh0 = rng.gamma(1.0, 1.0, (p.I, p.J))
@@ -121,42 +122,52 @@ def test_explicit_initial_state():
     ref = oracle_accel(p, 10, rh0=rh0.astype(np.float32).astype(np.float64),
                        ru0=ru0.astype(np.float32).astype(np.float64),
                        lam0=lam0.astype(np.float32).astype(np.float64))
-    out = gpu_run(p, 10, init_arrays=dict(rh0=rh0, ru0=ru0, lam0=lam0))[0]
-    assert_close(out, ref, what="explicit init")
+    out = gpu_run(p, 10, init_arrays=dict(rh0=rh0, ru0=ru0, lam0=lam0), fused=fused)[0]
+    assert_close(out, ref, what=f"explicit init fused={fused}")
 
 
-def test_zero_iterations_returns_init(c0):
-    out = gpu_run(c0, 0)[0]
+@pytest.mark.parametrize("fused", [False, True])
+def test_zero_iterations_returns_init(c0, fused):
+    out = gpu_run(c0, 0, fused=fused)[0]
     assert np.all(out["rh"] == 1.0) and np.all(out["ru"] == 1.0) and np.all(out["lam"] == 1.0)
 
 
-def test_degenerate_zero_observations():
+@pytest.mark.parametrize("fused", [False, True])
+def test_degenerate_zero_observations(fused):
     p = make_problem(3, 2, 65, config=431)
     p.x[0, 10:20] = 0  # silent frames are legal: r^u decays but stays positive
     ref = oracle_accel(p, 10)
-    out = gpu_run(p, 10)[0]
+    out = gpu_run(p, 10, fused=fused)[0]
     assert_close(out, ref, what="zero frames")
     assert np.all(out["ru"] > 0) and np.all(out["rh"] > 0)
 
 
-def test_prior_ml_mode():
+@pytest.mark.parametrize("fused", [False, True])
+def test_prior_ml_mode(fused):
     p = make_problem(4, 4, 100, config=432)
     ref = oracle_accel(p, 10, alpha=-1.0, beta=0.0)
-    out = gpu_run(p, 10, alpha=-1.0, beta=0.0)[0]
+    out = gpu_run(p, 10, alpha=-1.0, beta=0.0, fused=fused)[0]
     assert_close(out, ref, what="ML mode")
 
 
-def test_data_errors_are_reported():
+@pytest.mark.parametrize("fused", [False, True])
+def test_data_errors_are_reported(fused):
     import torch
 
     from paper_1908_01964_amd import Context, RcscmError, to_device
     p = make_problem(4, 3, 50, config=433)
     x, a, Rp, b = to_device(p)
+
+    def go(ctx, xx, bb_, K):  # init + iterate, or the single call rcscm_run
+        if fused:
+            ctx.run(xx, a, Rp, bb_, K)
+        else:
+            ctx.init(xx, a, Rp, bb_).iterate(K)
     # non-finite observation
     xb = x.clone()
     xb[7] = float("nan")
     ctx = Context.single(p.I, p.J, p.M)
-    ctx.init(xb, a, Rp, b).iterate(2)
+    go(ctx, xb, b, 2)
     with pytest.raises(RcscmError) as ei:
         ctx.sync()
     assert ei.value.status == -5
@@ -165,14 +176,14 @@ def test_data_errors_are_reported():
     bb = b.clone().reshape(p.I, p.M)
     bb[1] = torch.tensor([1, 0, 0, 0], dtype=torch.complex128)
     ctx = Context.single(p.I, p.J, p.M)
-    ctx.init(x, a, Rp, bb.reshape(-1)).iterate(1)
+    go(ctx, x, bb.reshape(-1), 1)
     with pytest.raises(RcscmError) as ei:
         ctx.sync()
     assert ei.value.status == -3 and "frequency 1" in str(ei.value)
     ctx.close()
     # a non-unit b is normalised, not an error
     ctx = Context.single(p.I, p.J, p.M)
-    ctx.init(x, a, Rp, b * 3.0).iterate(5)
+    go(ctx, x, b * 3.0, 5)
     o3 = ctx.extract()
     ctx.sync()
     ctx.close()
