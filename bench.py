@@ -95,6 +95,19 @@ def _oracle_rows(args):
     return list(freqs), rh, ru, lam, sh, t_acc, t_nv
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(I, J, K, reps, cores):
     """Times the FP64 oracle on the host cores; returns (report, FP64 reference arrays)."""
     import multiprocessing as mp
@@ -132,6 +145,7 @@ def cpu_baseline(I, J, K, reps, cores):
     naive_rate = acc_rate * t_acc_rows / t_nv_rows
     report = {
         "value": acc_rate, "unit": "TF-bin updates/s", "cores": cores, "kind": "oracle",
+        "cpu": cpu_model(),
         "sample": (f"the full workload (I={I}, J={J}, K={K}), FP64 numpy oracle of the "
                    f"second-stage rule incl. precompute and extraction, rows split over "
                    f"{cores} processes x 1 thread, median of {len(walls)} runs "
@@ -455,6 +469,8 @@ def main():
                 "kernel": "accel_fused_kernel", "launch_us": run_us,
                 "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": updates,
                 "hbm_GBps_algorithmic": (bytes_bin * nbins / (run_us * 1e-6) / 1e9
+                                         if bytes_bin else None),
+                "hbm_frac_algorithmic": (bytes_bin * nbins / (run_us * 1e-6) / 1e9 / PEAK_HBM_GBS
                                          if bytes_bin else None),
                 "algorithmic_bytes_per_bin": bytes_bin}
     elif used["schedule"] == "resident":

@@ -120,6 +120,8 @@ void fused_launch_m(hipStream_t s, int nt, int bpl, int nrows, const FusedArgs& 
   RCSCM_FU(256, 2)
   RCSCM_FU(256, 4)
   RCSCM_FU(256, 8)
+  RCSCM_FU(512, 4)
+  RCSCM_FU(512, 8)
   RCSCM_FU(1024, 4)
   RCSCM_FU(1024, 8)
 #undef RCSCM_FU
