@@ -312,32 +312,6 @@ __global__ __launch_bounds__(256) void objective_kernel(
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// -------------------------------------------------------------- FILL STATE --
-
-__global__ __launch_bounds__(256) void fill_state_kernel(
-    int nrows, const RowInfo* __restrict__ rows, const float* __restrict__ rh0,
-    const float* __restrict__ ru0, const float* __restrict__ lam0, float rh_c, float ru_c,
-    float lam_c, float* __restrict__ rh, float* __restrict__ ru, float* __restrict__ lam,
-    unsigned* __restrict__ status) {
-  const int row = blockIdx.x;
-  const RowInfo ri = rows[row];
-  bool bad = false;
-  for (int j = threadIdx.x; j < ri.J; j += blockDim.x) {
-    const long long bin = ri.bin_off + j;
-    const float h = rh0 ? rh0[bin] : rh_c;
-    const float u = ru0 ? ru0[bin] : ru_c;
-    rh[bin] = h;
-    ru[bin] = u;
-    bad = bad || !(h > 0.0f) || !(u > 0.0f) || !isfinite(h) || !isfinite(u);
-  }
-  if (threadIdx.x == 0) {
-    const float l = lam0 ? lam0[row] : lam_c;
-    lam[row] = l;
-    if (!(l > 0.0f) || !isfinite(l)) bad = true;
-  }
-  if (bad) atomicOr(status + row, ST_NONFINITE_STATE);
-}
-
 }  // namespace
 
 bool resident_supported(int nt, int bpl) {
@@ -408,14 +382,6 @@ void launch_objective(hipStream_t s, int nchunks, const ChunkInfo* chunks, const
   if (nchunks <= 0) return;
   hipLaunchKernelGGL(objective_kernel, dim3(nchunks), dim3(256), 0, s, chunks, rows, rcf, rcd,
                      tsig, nu, rh, ru, lam, alpha, beta, partial);
-}
-
-void launch_fill_state(hipStream_t s, int nrows, const RowInfo* rows, const float* rh0,
-                       const float* ru0, const float* lam0, float rh_c, float ru_c, float lam_c,
-                       float* rh, float* ru, float* lam, unsigned* status) {
-  if (nrows <= 0) return;
-  hipLaunchKernelGGL(fill_state_kernel, dim3(nrows), dim3(256), 0, s, nrows, rows, rh0, ru0, lam0,
-                     rh_c, ru_c, lam_c, rh, ru, lam, status);
 }
 
 }  // namespace rcscm
