@@ -322,3 +322,16 @@ def test_first_stage_config1_sampled_rows():
     e = errors(got, ref)
     print("config1 first-stage (sampled)", e)
     assert all(v < 1e-3 for v in e.values()), e
+
+
+def test_rows_longer_than_a_workgroup():
+    """J = 9000 > 8192: AUTO falls back to STREAM, rcscm_run to the three calls; RESIDENT is refused."""
+    from paper_1908_01964_amd import Context, RcscmError
+    p = make_problem(2, 2, 9000, config=470, spatial="sinc", n_fft=4)
+    ref = oracle_accel(p, 6)
+    out = gpu_run(p, 6)[0]
+    assert_close(out, ref, what="J=9000 auto")
+    out = gpu_run(p, 6, fused=True)[0]
+    assert_close(out, ref, what="J=9000 run")
+    with pytest.raises(RcscmError):
+        Context.single(p.I, p.J, p.M, schedule="resident")
