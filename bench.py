@@ -291,10 +291,8 @@ def bench_adjoint(args):
     grh = torch.empty(nbins, dtype=torch.float32, device=dev)
     glam = torch.empty(I, dtype=torch.float32, device=dev)
 
-    def forward():
-        ctx.init(x, a, Rp, b, rh0=rh0, lam0=lam0)
-        ctx.iterate(K)
-        ctx.extract(out=out)
+    def forward():  # one rcscm_run keeping theta_k for the adjoint
+        ctx.run(x, a, Rp, b, K, rh0=rh0, lam0=lam0, out=out)
 
     forward()
     g = (2.0 * (out["s_hat"] - s_true)).contiguous()  # upstream gradient of sum |s_hat - s|^2
@@ -334,7 +332,7 @@ def bench_adjoint(args):
         "config": {"workload": "sinc-coherence M=4 I=513 J=1000 K=10, forward + adjoint "
                                "(loss sum |s_hat - s|^2)", "I": I, "J": J, "M": M, "K": K,
                    "bins": nbins, "schedule": used,
-                   "step": "init+iterate(K, checkpointed)+extract+backward"},
+                   "step": "run (setup, precompute, K iterations keeping theta_k, extraction) + backward"},
         "phases_us": {"forward": fw, "backward": bw},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,

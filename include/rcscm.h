@@ -163,10 +163,12 @@ rcscm_status rcscm_iterate(rcscm_ctx* ctx, int K);
 rcscm_status rcscm_extract(rcscm_ctx* ctx, float* rh, float* ru, float* lam, void* s_hat);
 
 /* init + iterate(K) + extract in one call (same arguments and outputs as
- * those three calls).  For the ACCEL rule with every J_u <= 8192, the F64
- * lambda sum and no checkpoints, each row runs its whole path - FP64 setup,
- * FP64 precomputation, K iterations, extraction - in one workgroup of one
- * launch per (M, workgroup size) class, reading x once and writing the
+ * those three calls).  For the ACCEL rule with every J_u <= 8192 and the F64
+ * lambda sum (with RCSCM_FLAG_CHECKPOINT: under the RESIDENT schedule, and
+ * theta_k is kept for rcscm_backward as iterate keeps it), each row runs its
+ * whole path - FP64 setup, FP64 precomputation, K iterations, extraction -
+ * in one workgroup of one launch per (M, workgroup size) class, reading x
+ * once and writing the
  * results once; otherwise the three calls are made in turn.  With several
  * classes the launches are spread over up to three library-owned
  * non-blocking streams that fork from and join back into the context's

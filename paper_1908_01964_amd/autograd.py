@@ -21,10 +21,9 @@ class _EstimateExtract(torch.autograd.Function):
     def forward(ctx, x, rh0, lam0, a, Rp, b, shape, K, ru0, params):
         I, Js, Ms = shape
         c = Context(I, Js, Ms, checkpoint=True, **params)
-        c.init(x.detach().contiguous(), a.contiguous(), Rp.contiguous(), b.contiguous(),
-               rh0=rh0.detach().contiguous(), ru0=ru0, lam0=lam0.detach().contiguous())
-        c.iterate(K)
-        out = c.extract()
+        # setup, precompute, K iterations (keeping theta_k) and extraction: one call
+        out = c.run(x.detach().contiguous(), a.contiguous(), Rp.contiguous(), b.contiguous(), K,
+                    rh0=rh0.detach().contiguous(), ru0=ru0, lam0=lam0.detach().contiguous())
         ctx.rcscm = c
         ctx.save_for_backward(x)
         ctx.mark_non_differentiable(out["rh"], out["ru"], out["lam"])

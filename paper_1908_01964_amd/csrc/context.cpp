@@ -594,6 +594,16 @@ static rcscm_status enqueue_stream_loop(rcscm_ctx* c, int K) {
   return RCSCM_OK;
 }
 
+// Checkpoint storage for K iterations (theta_k, k < K), grown on demand.
+static rcscm_status ensure_checkpoints(rcscm_ctx* c, int K) {
+  if (K <= c->ck_capacity) return RCSCM_OK;
+  RCSCM_TRY(c->alloc(&c->d_ck_rh, (size_t)K * c->nbins, "checkpoints r^h"));
+  RCSCM_TRY(c->alloc(&c->d_ck_ru, (size_t)K * c->nbins, "checkpoints r^u"));
+  RCSCM_TRY(c->alloc(&c->d_ck_lam, (size_t)K * c->nrows, "checkpoints lambda"));
+  c->ck_capacity = K;
+  return RCSCM_OK;
+}
+
 rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
   if (!c) return RCSCM_EINVAL;
   if (K < 0) return c->fail(RCSCM_ESHAPE, "K must be >= 0");
@@ -634,12 +644,7 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
   if (c->schedule == RCSCM_SCHED_RESIDENT) {
     float *ck_rh = nullptr, *ck_ru = nullptr, *ck_lam = nullptr;
     if (c->p.flags & RCSCM_FLAG_CHECKPOINT) {
-      if (K > c->ck_capacity) {
-        RCSCM_TRY(c->alloc(&c->d_ck_rh, (size_t)K * c->nbins, "checkpoints r^h"));
-        RCSCM_TRY(c->alloc(&c->d_ck_ru, (size_t)K * c->nbins, "checkpoints r^u"));
-        RCSCM_TRY(c->alloc(&c->d_ck_lam, (size_t)K * c->nrows, "checkpoints lambda"));
-        c->ck_capacity = K;
-      }
+      RCSCM_TRY(ensure_checkpoints(c, K));
       ck_rh = c->d_ck_rh;
       ck_ru = c->d_ck_ru;
       ck_lam = c->d_ck_lam;
@@ -844,8 +849,11 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   if (!c) return RCSCM_EINVAL;
   if (K < 0) return c->fail(RCSCM_ESHAPE, "K must be >= 0");
   if (!x || !a || !Rp || !b) return c->fail(RCSCM_EINVAL, "x, a, Rp and b must not be NULL");
+  // with checkpoints the adjoint walks the RESIDENT classes, so the fused path
+  // keeps them only under that schedule
+  const bool ckpt = (c->p.flags & RCSCM_FLAG_CHECKPOINT) != 0;
   const bool fused = !c->fused_classes.empty() && c->p.lamsum == RCSCM_LAMSUM_F64 &&
-                     !(c->p.flags & RCSCM_FLAG_CHECKPOINT);
+                     (!ckpt || c->schedule == RCSCM_SCHED_RESIDENT);
   if (!fused) {  // the same path as separate calls
     RCSCM_TRY(rcscm_init(c, x, a, Rp, b, rh0, ru0, lam0));
     RCSCM_TRY(rcscm_iterate(c, K));
@@ -880,6 +888,17 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   A.inv_a2 = (float)(1.0 / (c->p.alpha + 2.0));
   A.beta_a2 = (float)(c->p.beta / (c->p.alpha + 2.0));
   A.K = K;
+  A.ck_rh = A.ck_ru = A.ck_lam = nullptr;
+  A.ck_sb = 0;
+  A.ck_sr = 0;
+  if (ckpt) {
+    RCSCM_TRY(ensure_checkpoints(c, K));
+    A.ck_rh = c->d_ck_rh;
+    A.ck_ru = c->d_ck_ru;
+    A.ck_lam = c->d_ck_lam;
+    A.ck_sb = c->nbins;
+    A.ck_sr = c->nrows;
+  }
   c->chunk_status_valid = false;  // the fused kernel reports through status[row] only
   // Largest class first on the context's stream; the others go round-robin to
   // up to three auxiliary streams, so the tail of one class launch overlaps
@@ -922,7 +941,7 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   }
   c->x_borrowed = static_cast<const float2*>(x);
   c->inited = true;
-  c->ck_K = -1;
+  c->ck_K = ckpt ? K : -1;
   return RCSCM_OK;
 }
 

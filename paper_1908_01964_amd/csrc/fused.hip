@@ -82,8 +82,8 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   }
   const float lam0 = A.lam0 ? A.lam0[row] : A.lam_c;
   const float lam_fin = resident_iterations<NT, BPL, 0>(ts, vnu, vrh, vru, rc, lam0, row, J, base,
-                                                        A.K, A.inv_a2, A.beta_a2, red, nullptr,
-                                                        nullptr, nullptr, 0, 0);
+                                                        A.K, A.inv_a2, A.beta_a2, red, A.ck_rh,
+                                                        A.ck_ru, A.ck_lam, A.ck_sb, A.ck_sr);
   const LamTerms Lf = lam_terms(rc, lam_fin);
 #pragma unroll
   for (int q = 0; q < BPL; ++q) {

@@ -127,6 +127,13 @@ struct FusedArgs {
   float* ru_out;
   float* lam_out;
   float2* s_hat;
+  // theta at the start of every iteration for the adjoint ([k][bin], [k][row];
+  // null: not kept)
+  float* ck_rh;
+  float* ck_ru;
+  float* ck_lam;
+  long long ck_sb;
+  int ck_sr;
   float inv_a2, beta_a2;
   int K;
 };

@@ -88,3 +88,28 @@ def test_backward_requires_checkpoints():
         c.backward(x, torch.zeros(p.I * p.J, dtype=torch.complex64, device="cuda"))
     assert ei.value.status == -8
     c.close()
+
+
+def test_backward_after_run_equals_after_separate_calls():
+    """Checkpoints kept by the fused rcscm_run drive the same adjoint as init + iterate + extract."""
+    import torch
+
+    from paper_1908_01964_amd import Context, to_device
+    p = make_problem(4, 6, 700, config=511, spatial="sinc", n_fft=16)
+    x, a, Rp, b = to_device(p)
+    K = 6
+    g = torch.randn(p.I * p.J, dtype=torch.complex64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(5))
+    grads = []
+    for fused in (False, True):
+        c = Context.single(p.I, p.J, p.M, checkpoint=True, schedule="resident", block=256)
+        if fused:
+            c.run(x, a, Rp, b, K)
+        else:
+            c.init(x, a, Rp, b).iterate(K)
+            c.extract()
+        grads.append([t.cpu() for t in c.backward(x, g)])
+        c.sync()
+        c.close()
+    for u, v in zip(*grads):
+        assert torch.equal(u, v)
