@@ -39,8 +39,55 @@ __device__ __forceinline__ double block_sum(double v, uint64_t (*red)[NT / 64], 
   return s;
 }
 
+// x_bar of the lane's bins: c T_bar' + b B_bar + 2 nu_bar (R')^+ x in FP64,
+// with T_bar' = T_bar - 2 tau^ax nu_bar / tau^aa and (R')^+ (row-major M x M),
+// c, b staged in LDS (re-read per bin rather than held in registers).
+template <int M, int NT, int BPL>
+__device__ __forceinline__ void xbar_bins(const float2* __restrict__ xr0,
+                                          float2* __restrict__ gx0, int J,
+                                          const float4 (&ts)[BPL], const float (&Tbr)[BPL],
+                                          const float (&Tbi)[BPL], const float (&Bbr)[BPL],
+                                          const float (&Bbi)[BPL], const float (&nub)[BPL],
+                                          double inv_taad, const double2* sQ, const double2* sc,
+                                          const double2* sbv) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < BPL; ++q) {
+    const int j = t + q * NT;
+    if (j >= J) continue;
+    const double nb = nub[q];
+    const double tr = (double)Tbr[q] - 2.0 * (double)ts[q].x * nb * inv_taad;
+    const double ti = (double)Tbi[q] - 2.0 * (double)ts[q].y * nb * inv_taad;
+    const float2* xp = xr0 + (long long)j * M;
+    float2* gp = gx0 + (long long)j * M;
+    double xr[M], xi[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const float2 v = xp[m];
+      xr[m] = v.x;
+      xi[m] = v.y;
+    }
+    asm volatile("" ::: "memory");  // keep (R')^+ in LDS
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double yr = 0.0, yi = 0.0;  // ((R')^+ x)_m
+#pragma unroll
+      for (int n = 0; n < M; ++n) {
+        const double2 Qmn = sQ[m * M + n];
+        yr = fma(Qmn.x, xr[n], fma(-Qmn.y, xi[n], yr));
+        yi = fma(Qmn.x, xi[n], fma(Qmn.y, xr[n], yi));
+      }
+      const double2 c = sc[m], b = sbv[m];
+      const double gr = c.x * tr - c.y * ti + b.x * Bbr[q] - b.y * Bbi[q] + 2.0 * nb * yr;
+      const double gi = c.x * ti + c.y * tr + b.x * Bbi[q] + b.y * Bbr[q] + 2.0 * nb * yi;
+      gp[m] = make_float2((float)gr, (float)gi);
+    }
+  }
+}
+
 template <int NT, int BPL>
-__global__ __launch_bounds__(NT) void backward_kernel(
+// (up to 4 bins per lane: at least four waves per SIMD)
+__global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
     const int* __restrict__ row_list, const RowInfo* __restrict__ rows,
     const RowConstF* __restrict__ rcf, const RowConstD* __restrict__ rcd,
     const float2* __restrict__ x, const float4* __restrict__ tsig, const float* __restrict__ nu,
@@ -86,11 +133,12 @@ __global__ __launch_bounds__(NT) void backward_kernel(
       const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
       const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
       const float D = fmaf(h, A, u);
-      const float gam = h / D;
+      const float iD = frcp(D);
+      const float gam = h * iD;
       const float gbar = Pr * gs.x + Pi * gs.y;
       const float Pbr = gam * gs.x, Pbi = gam * gs.y;
-      const float Dbar = -gbar * gam / D;
-      hb[q] = gbar / D + Dbar * A;
+      const float Dbar = -gbar * gam * iD;
+      hb[q] = fmaf(gbar, iD, Dbar * A);
       ub[q] = Dbar;
       const float Abar = Dbar * h;
       Tbr[q] += Pbr;
@@ -106,36 +154,66 @@ __global__ __launch_bounds__(NT) void backward_kernel(
     lam_bar = (float)(-(double)il * (double)il * ilbar);
   }
 
-  // ---- iterations, last to first
+  // ---- iterations, last to first; theta_k is loaded one iteration ahead
+  float nh[BPL], nu_[BPL];
+  if (K > 0) {
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      const int j = t + q * NT;
+      const bool on = j < J;
+      nh[q] = on ? ck_rh[(long long)(K - 1) * sb + base + j] : 1.f;
+      nu_[q] = on ? ck_ru[(long long)(K - 1) * sb + base + j] : 1.f;
+    }
+  }
   for (int k = K - 1; k >= 0; --k) {
     const float lam = ck_lam[(long long)k * sr + row];
     const float lam_n = (k + 1 < K) ? ck_lam[(long long)(k + 1) * sr + row] : lam_fin[row];
     const float il = frcp_nr(lam), il_n = frcp_nr(lam_n);
     const float A = fmaf(S2, il, taa), A_n = fmaf(S2, il_n, taa);
     float vh[BPL], vu[BPL];
-    double c1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      vh[q] = nh[q];
+      vu[q] = nu_[q];
+    }
+    if (k > 0) {  // prefetch theta_{k-1}
+#pragma unroll
+      for (int q = 0; q < BPL; ++q) {
+        const int j = t + q * NT;
+        const bool on = j < J;
+        nh[q] = on ? ck_rh[(long long)(k - 1) * sb + base + j] : 1.f;
+        nu_[q] = on ? ck_ru[(long long)(k - 1) * sb + base + j] : 1.f;
+      }
+    }
+    // phase-A quantities of iteration k kept for the second pass (the cheap
+    // ones are recomputed there)
+    constexpr bool kKeep = BPL <= 4;  // registers allow it up to 4 bins per lane
+    float viD[BPL], vg[BPL], vE[BPL];
+    float c1 = 0.0f;  // the lane's terms in float, lanes in double
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       const int j = t + q * NT;
-      const bool on = j < J;
-      vh[q] = on ? ck_rh[(long long)k * sb + base + j] : 1.f;
-      vu[q] = on ? ck_ru[(long long)k * sb + base + j] : 1.f;
       const float4 T = ts[q];
       const float h = vh[q], u = vu[q];
       const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
       const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
-      const float D = fmaf(h, A, u);
-      const float g = h / D;
+      const float iD = frcp(fmaf(h, A, u));
+      const float g = h * iD;
       const float wr = g * Pr, wi = g * Pi;
       const float er = T.z - (sr_ * wr + si_ * wi), ei = T.w - (sr_ * wi - si_ * wr);
       const float E = er * er + ei * ei;
-      if (on) c1 += (double)(ub[q] * invM * fmaf(S2, g * u, E));
+      if constexpr (kKeep) {
+        viD[q] = iD;
+        vg[q] = g;
+        vE[q] = E;
+      }
+      if (j < J) c1 += ub[q] * invM * fmaf(S2, g * u, E);
     }
-    const double ilnbar = block_sum<NT>(c1, red, phase);
+    const double ilnbar = block_sum<NT>((double)c1, red, phase);
     const float lam_n_bar = (float)((double)lam_bar - (double)il_n * (double)il_n * ilnbar);
     const float tbar = lam_n_bar * rc.invJ;
 
-    double c2 = 0.0;
+    float c2 = 0.0f;
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       const int j = t + q * NT;
@@ -143,13 +221,14 @@ __global__ __launch_bounds__(NT) void backward_kernel(
       const float h = vh[q], u = vu[q];
       const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
       const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
-      const float D = fmaf(h, A, u);
-      const float g = h / D;
+      const float iD = kKeep ? viD[q] : frcp(fmaf(h, A, u));
+      const float g = kKeep ? vg[q] : h * iD;
+      const float iu = frcp(u);
       const float R2 = Pr * Pr + Pi * Pi;
       const float Q = fmaf(g, R2, u);
       const float wr = g * Pr, wi = g * Pi;
       const float er = T.z - (sr_ * wr + si_ * wi), ei = T.w - (sr_ * wi - si_ * wr);
-      const float E = er * er + ei * ei;
+      const float E = kKeep ? vE[q] : fmaf(er, er, ei * ei);
       const float dr = T.x - wr * taa, di = T.y - wi * taa;
       // r^u_{k+1} = (g u A_n + nu + |d|^2 / taa + E / lambda_n) / M
       const float uu = ub[q] * invM;
@@ -161,8 +240,8 @@ __global__ __launch_bounds__(NT) void backward_kernel(
       float Ebar = uu * il_n;
       // lambda_{k+1} = mean_j (g S2 + E / u)
       gbar += S2 * tbar;
-      Ebar += tbar / u;
-      ubar -= E / (u * u) * tbar;
+      Ebar += tbar * iu;
+      ubar -= E * iu * iu * tbar;
       // d = T - w taa
       Tbr[q] += dbr;
       Tbi[q] += dbi;
@@ -186,8 +265,8 @@ __global__ __launch_bounds__(NT) void backward_kernel(
       Pbr += 2.0f * Pr * (Qbar * g);
       Pbi += 2.0f * Pi * (Qbar * g);
       // g = h / D ; D = u + h A
-      float hbar = gbar / D;
-      const float Dbar = -gbar * g / D;
+      float hbar = gbar * iD;
+      const float Dbar = -gbar * g * iD;
       ubar += Dbar;
       hbar += Dbar * A;
       // P = T + s B il
@@ -196,11 +275,11 @@ __global__ __launch_bounds__(NT) void backward_kernel(
       Bbr[q] += il * (sr_ * Pbr + si_ * Pbi);
       Bbi[q] += il * (sr_ * Pbi - si_ * Pbr);
       const float sBr = sr_ * T.z - si_ * T.w, sBi = sr_ * T.w + si_ * T.z;
-      if (j < J) c2 += (double)(sBr * Pbr + sBi * Pbi) + (double)(S2 * Dbar * h);
+      if (j < J) c2 += sBr * Pbr + sBi * Pbi + S2 * Dbar * h;
       hb[q] = hbar;
       ub[q] = ubar;
     }
-    const double ilbar = block_sum<NT>(c2, red, phase);
+    const double ilbar = block_sum<NT>((double)c2, red, phase);
     lam_bar = (float)(-(double)il * (double)il * ilbar);
   }
 
@@ -209,46 +288,36 @@ __global__ __launch_bounds__(NT) void backward_kernel(
   // ---- precomputation: x_bar = c T_bar' + b B_bar + 2 nu_bar (R')^+ x
   const RowConstD* Dc = rcd + row;
   const int M = ri.M;
+  __shared__ double2 sQ[MAXM * MAXM], sc[MAXM], sbv[MAXM];
+  for (int e = t; e < M * M; e += NT) sQ[e] = Dc->Q[(e / M) * MAXM + e % M];
+  if (t < M) {
+    sc[t] = Dc->c[t];
+    sbv[t] = Dc->b[t];
+  }
+  __syncthreads();
   const double taad = Dc->t_aa;
   const double inv_taad = taad > 0.0 ? 1.0 / taad : 0.0;
 #pragma unroll
   for (int q = 0; q < BPL; ++q) {
     const int j = t + q * NT;
-    if (j >= J) continue;
-    if (grad_rh0 != nullptr) grad_rh0[base + j] = hb[q];
-    if (grad_x == nullptr) continue;
-    const float4 T = ts[q];
-    const double nb = nub[q];
-    const double tr = (double)Tbr[q] - 2.0 * (double)T.x * nb * inv_taad;
-    const double ti = (double)Tbi[q] - 2.0 * (double)T.y * nb * inv_taad;
-    const float2* xp = x + ri.x_off + (long long)j * M;
-    double xr[MAXM], xi[MAXM];
-#pragma unroll
-    for (int m = 0; m < MAXM; ++m) {
-      const float2 v = (m < M) ? xp[m] : make_float2(0.f, 0.f);
-      xr[m] = v.x;
-      xi[m] = v.y;
-    }
-    float2* gp = grad_x + ri.x_off + (long long)j * M;
-#pragma unroll
-    for (int m = 0; m < MAXM; ++m) {
-      if (m >= M) continue;
-      // ((R')^+ x)_m = sum_n Q[m][n] x_n
-      double yr = 0.0, yi = 0.0;
-#pragma unroll
-      for (int n = 0; n < MAXM; ++n) {
-        if (n < M) {
-          const double2 Qmn = Dc->Q[m * MAXM + n];
-          yr = fma(Qmn.x, xr[n], fma(-Qmn.y, xi[n], yr));
-          yi = fma(Qmn.x, xi[n], fma(Qmn.y, xr[n], yi));
-        }
-      }
-      const double2 c = Dc->c[m];
-      const double2 b = Dc->b[m];
-      const double gr = c.x * tr - c.y * ti + b.x * Bbr[q] - b.y * Bbi[q] + 2.0 * nb * yr;
-      const double gi = c.x * ti + c.y * tr + b.x * Bbi[q] + b.y * Bbr[q] + 2.0 * nb * yi;
-      gp[m] = make_float2((float)gr, (float)gi);
-    }
+    if (j < J && grad_rh0 != nullptr) grad_rh0[base + j] = hb[q];
+  }
+  if (grad_x == nullptr) return;
+  switch (M) {
+#define RCSCM_XB(MM)                                                                         \
+  case MM:                                                                                   \
+    xbar_bins<MM, NT, BPL>(x + ri.x_off, grad_x + ri.x_off, J, ts, Tbr, Tbi, Bbr, Bbi, nub,    \
+                           inv_taad, sQ, sc, sbv);                                           \
+    break;
+    RCSCM_XB(2)
+    RCSCM_XB(3)
+    RCSCM_XB(4)
+    RCSCM_XB(5)
+    RCSCM_XB(6)
+    RCSCM_XB(7)
+    RCSCM_XB(8)
+#undef RCSCM_XB
+    default: break;
   }
 }
 
