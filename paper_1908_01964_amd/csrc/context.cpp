@@ -675,11 +675,14 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
       hipError_t e2 = hipStreamEndCapture(cap, &g);
       c->stream = saved;
       (void)hipStreamDestroy(cap);
-      if (e != hipSuccess || e2 != hipSuccess || st != RCSCM_OK)
+      if (e != hipSuccess || e2 != hipSuccess || st != RCSCM_OK) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
         return c->fail(RCSCM_EDEVICE, "hipGraph capture of the iteration loop failed");
+      }
+      c->graph_defs.push_back(g);  // owned by the context from here on
       hipGraphExec_t ex = nullptr;
       RCSCM_HIP(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-      c->graph_defs.push_back(g);
       it = c->graphs.emplace(key, ex).first;
     }
     RCSCM_HIP(c, hipGraphLaunch(it->second, s));
@@ -830,16 +833,25 @@ static rcscm_status ensure_aux(rcscm_ctx* c, int n) {
   int cur = 0;
   RCSCM_HIP(c, hipGetDevice(&cur));
   if (cur != c->device) RCSCM_HIP(c, hipSetDevice(c->device));
+  struct Restore {  // the caller's current device, also on the error paths
+    int dev, ctx_dev;
+    ~Restore() {
+      if (dev != ctx_dev) (void)hipSetDevice(dev);
+    }
+  } restore{cur, c->device};
   if (!c->ev_fork) RCSCM_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   while ((int)c->aux.size() < n) {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
-    RCSCM_HIP(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    c->aux.push_back(st);
     RCSCM_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipEventDestroy(ev);
+      return c->fail(RCSCM_EDEVICE, "hipStreamCreateWithFlags failed");
+    }
+    c->aux.push_back(st);
     c->ev_join.push_back(ev);
   }
-  if (cur != c->device) RCSCM_HIP(c, hipSetDevice(cur));
   return RCSCM_OK;
 }
 

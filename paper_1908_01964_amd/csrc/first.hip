@@ -115,14 +115,14 @@ __global__ __launch_bounds__(kFirstNT) void first_stage_kernel(
         pi = fmaf(sd[m].x, xv[q][m].y, fmaf(-sd[m].y, xv[q][m].x, pi));
       }
       const float h = vrh[q], u = vru[q];
-      const float gg = h / fmaf(h, rho_aa_t, u);
+      const float gg = h * frcp(fmaf(h, rho_aa_t, u));
       const float r2 = fmaf(pr, pr, pi * pi);
       vrh[q] = fmaf(gg * fmaf(gg, r2, u), inv_a2, beta_a2);
       // e = sigma^bx - gamma~ conj(sigma^ab) rho~ax
       const float wr = gg * pr, wi = gg * pi;
       const float er = sbr[q] - fmaf(rc.sab_re, wr, rc.sab_im * wi);
       const float ei = sbi[q] - fmaf(rc.sab_re, wi, -rc.sab_im * wr);
-      if (t + q * kFirstNT < J) acc.add(fmaf(gg, rc.sab2, fmaf(er, er, ei * ei) / u));
+      if (t + q * kFirstNT < J) acc.add(fmaf(gg, rc.sab2, fmaf(er, er, ei * ei) * frcp(u)));
       g[q] = gg;
       rxr[q] = pr;
       rxi[q] = pi;

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kNT) void naive_a_kernel(
         }
       }
     }
-    acc.add(bUb / u);
+    acc.add(bUb * frcp(u));
   }
   acc = wave_allreduce<0>(acc);
   if ((t & 63) == 0) red[t >> 6] = acc.pack();
