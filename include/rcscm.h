@@ -17,8 +17,10 @@
  *   RCSCM_RULE_NAIVE - the literal E-step/M-step (eqs. (13)-(20)) with an
  *                      M x M factorisation of the model covariance per bin.
  *   RCSCM_RULE_FIRST - the first-stage accelerated rule (Algorithm 1,
- *                      eqs. (27)-(45)): two M x M inverses per frequency and
- *                      O(M^2) quadratic forms per bin per iteration; needs
+ *                      eqs. (27)-(45)): the inverses of R~_i and R_i per
+ *                      frequency (R~ of an iteration is R of the previous
+ *                      one, so one M x M inversion per iteration) and O(M^2)
+ *                      quadratic forms per bin per iteration; needs
  *                      J_u <= 4096.
  *
  * Conventions for every entry point:

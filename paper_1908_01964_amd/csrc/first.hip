@@ -11,9 +11,10 @@
 //   r^u    = (gamma~ rho^aa (r~u + gamma~|rho~ax|^2) + rho^xx
 //             - 2 gamma~ Re[rho~ax conj(rho^ax)]) / M                eq. (45)
 // One workgroup per row keeps x (and sigma^bx, r^h, r^u) of its frames in
-// registers for all K iterations; wave 0 inverts the two M x M matrices per
-// iteration in FP64 (Gauss-Jordan in LDS); the per-bin work is float, O(M^2)
-// per bin for rho^xx.  x must stay valid (the context borrows it).
+// registers for all K iterations; wave 0 inverts R_i in FP64 once per
+// iteration (Gauss-Jordan in LDS; R~ of the next iteration is the same matrix,
+// so its inverse is reused); the per-bin work is float, O(M^2) per bin for
+// rho^xx.  x must stay valid (the context borrows it).
 #include "accel_common.h"
 #include "small_linalg.h"
 
@@ -98,11 +99,12 @@ __global__ __launch_bounds__(kFirstNT) void first_stage_kernel(
     vru[q] = (j < J) ? ru[base + j] : 1.f;
   }
   float lam_t = lam[row];
+  // R~^{-1} of the first iteration; later iterations reuse the R^{-1} of the
+  // previous one (R~_{k+1} = R' + lambda_k b b^H = R_k)
+  if (K > 0 && t < 64) row_inverse_wave<M>(D, (double)lam_t, aug, sRi, sd, &sraa);
+  __syncthreads();
 
   for (int k = 0; k < K; ++k) {
-    // R~^{-1} with the lambda at the start of the iteration
-    if (t < 64) row_inverse_wave<M>(D, (double)lam_t, aug, sRi, sd, &sraa);
-    __syncthreads();
     const float rho_aa_t = sraa;
     float g[BPL], rxr[BPL], rxi[BPL];
     LamAcc<0> acc;
@@ -162,7 +164,8 @@ __global__ __launch_bounds__(kFirstNT) void first_stage_kernel(
       vru[q] = (gg * rho_aa * fmaf(gg, r2, u) + rxx - 2.0f * gg * cross) * rc.invM;
     }
     lam_t = lam_n;
-    __syncthreads();  // sRi / sd are rewritten at the start of the next iteration
+    // sd, sraa now hold R~^{-1} of the next iteration; wave 0 rewrites them
+    // only after that iteration's frame-sum barrier
   }
   bool bad = false;
 #pragma unroll
