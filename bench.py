@@ -150,7 +150,7 @@ def cpu_baseline(I, J, K, reps, cores):
                    f"second-stage rule incl. precompute and extraction, rows split over "
                    f"{cores} processes x 1 thread, median of {len(walls)} runs "
                    f"({t:.2f} s each); naive-rule rate scaled from {len(sample)} rows "
-                   f"timed in the same workers ({wall_n:.1f} s)"),
+                   f"timed in the same workers ({wall_n:.2f} s)"),
         "naive_value": naive_rate,
         "accel_vs_naive": t_nv_rows / t_acc_rows,
     }
