@@ -212,13 +212,15 @@ def test_objective_matches_oracle_and_decreases(c0):
     ctx.close()
 
 
-def test_config1_full_size_accel():
-    """Config 1 at full size (M=4, I=513, J=1000, K=20), default schedule, every bin."""
+@pytest.mark.parametrize("fused", [True, False])
+def test_config1_full_size_accel(fused):
+    """Config 1 at full size (M=4, I=513, J=1000, K=20), every bin: the bench step (one fused
+    rcscm_run) and the three-call path with the default schedule."""
     p = config(1)
     ref = oracle_accel(p, 20)
-    out = gpu_run(p, 20)[0]
-    e = assert_close(out, ref, what="config 1")
-    print("config1 accel", e)
+    out = gpu_run(p, 20, fused=fused)[0]
+    e = assert_close(out, ref, what=f"config 1 fused={fused}")
+    print("config1 accel", fused, e)
 
 
 def test_config1_full_size_naive_sampled_rows():
