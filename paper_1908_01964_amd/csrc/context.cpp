@@ -133,6 +133,17 @@ struct rcscm_ctx {
     *out = static_cast<T*>(ptr);
     return RCSCM_OK;
   }
+  // Frees a buffer from alloc (the caller makes sure no queued work uses it).
+  template <class T>
+  void release(T** p) {
+    if (!*p) return;
+    for (auto& q : mem.ptrs)
+      if (q == static_cast<void*>(*p)) {
+        (void)hipFree(q);
+        q = nullptr;
+      }
+    *p = nullptr;
+  }
 };
 
 #define RCSCM_HIP(ctx, call)                                                            \
@@ -597,6 +608,13 @@ static rcscm_status enqueue_stream_loop(rcscm_ctx* c, int K) {
 // Checkpoint storage for K iterations (theta_k, k < K), grown on demand.
 static rcscm_status ensure_checkpoints(rcscm_ctx* c, int K) {
   if (K <= c->ck_capacity) return RCSCM_OK;
+  if (c->ck_capacity > 0) {  // replace the smaller buffers once queued work is done with them
+    RCSCM_HIP(c, hipStreamSynchronize(c->stream));
+    c->release(&c->d_ck_rh);
+    c->release(&c->d_ck_ru);
+    c->release(&c->d_ck_lam);
+    c->ck_capacity = 0;
+  }
   RCSCM_TRY(c->alloc(&c->d_ck_rh, (size_t)K * c->nbins, "checkpoints r^h"));
   RCSCM_TRY(c->alloc(&c->d_ck_ru, (size_t)K * c->nbins, "checkpoints r^u"));
   RCSCM_TRY(c->alloc(&c->d_ck_lam, (size_t)K * c->nrows, "checkpoints lambda"));

@@ -113,3 +113,27 @@ def test_backward_after_run_equals_after_separate_calls():
         c.close()
     for u, v in zip(*grads):
         assert torch.equal(u, v)
+
+
+def test_checkpoint_storage_grows():
+    """A longer second run replaces the checkpoint buffers; the adjoint then equals a fresh one."""
+    import torch
+
+    from paper_1908_01964_amd import Context, to_device
+    p = make_problem(3, 4, 300, config=512)
+    x, a, Rp, b = to_device(p)
+    g = torch.randn(p.I * p.J, dtype=torch.complex64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(6))
+    c1 = Context.single(p.I, p.J, p.M, checkpoint=True)
+    c1.run(x, a, Rp, b, 3)
+    c1.run(x, a, Rp, b, 8)
+    g1 = [t.cpu() for t in c1.backward(x, g)]
+    c1.sync()
+    c1.close()
+    c2 = Context.single(p.I, p.J, p.M, checkpoint=True)
+    c2.run(x, a, Rp, b, 8)
+    g2 = [t.cpu() for t in c2.backward(x, g)]
+    c2.sync()
+    c2.close()
+    for u, v in zip(g1, g2):
+        assert torch.equal(u, v)
