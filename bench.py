@@ -464,6 +464,8 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
                 "traffic": load_traffic() if args.workload == 1 else None,
+                # the chip's packed-FP32 figure, out of reach with packed FP32 compiled out
+                "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
                 "kernel": "accel_fused_kernel", "launch_us": run_us,
                 "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": updates,
                 "hbm_GBps_algorithmic": (bytes_bin * nbins / (run_us * 1e-6) / 1e9
