@@ -174,7 +174,10 @@ rcscm_status rcscm_extract(rcscm_ctx* ctx, float* rh, float* ru, float* lam, voi
  * results once; otherwise the three calls are made in turn.  With several
  * classes the launches are spread over up to three library-owned
  * non-blocking streams that fork from and join back into the context's
- * stream, so completion is still ordered on that stream.  Leaves the
+ * stream, so completion is still ordered on that stream.  The call can be
+ * captured into a HIP graph on the context's stream (it enqueues launches and
+ * event records/waits only); with several classes make one uncaptured call
+ * first, which creates the auxiliary streams.  Leaves the
  * context in the same state as the three calls (iterate/extract/objective
  * may follow).  Asynchronous. */
 rcscm_status rcscm_run(rcscm_ctx* ctx, const void* x, const void* a, const void* Rp,

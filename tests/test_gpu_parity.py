@@ -112,6 +112,49 @@ def test_graph_equals_eager(c0):
     cg.close()
 
 
+@pytest.mark.parametrize("batch", [False, True])
+def test_fused_run_captured_in_a_graph(batch):
+    """rcscm_run captured into a HIP graph (through torch.cuda.graph) and replayed: every replay,
+    with eager work and synchronisation between replays, equals the eager call bitwise.  The
+    batch has three workgroup classes, so the capture includes the fork to and join from the
+    auxiliary streams (created by the warm-up call)."""
+    import torch
+
+    from paper_1908_01964_amd import Context, to_device
+    if batch:
+        probs = [make_problem(m, 16, j, config=481, utterance=u, spatial="random")
+                 for u, (j, m) in enumerate([(300, 2), (1500, 4), (3000, 3)])]
+    else:
+        probs = [make_problem(4, 16, 600, config=480, spatial="sinc", n_fft=32)]
+    I = 16
+    Js = [q.J for q in probs]
+    Ms = [q.M for q in probs]
+    x, a, Rp, b = to_device(probs)
+    ref = Context(I, Js, Ms)
+    o_ref = ref.run(x, a, Rp, b, 7)
+    ref.sync()
+    s = torch.cuda.Stream()
+    ctx = Context(I, Js, Ms, stream=s)
+    out = {k: torch.empty_like(v) for k, v in o_ref.items()}
+    with torch.cuda.stream(s):
+        ctx.run(x, a, Rp, b, 7, out=out)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ctx.run(x, a, Rp, b, 7, out=out)
+    for rep in range(3):
+        for v in out.values():
+            v.fill_(float("nan"))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in o_ref:
+            assert torch.equal(out[k], o_ref[k]), (rep, k)
+    ctx.sync()
+    ctx.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("fused", [False, True])
 def test_explicit_initial_state(fused):
     p = make_problem(4, 5, 200, config=430)
