@@ -6,6 +6,8 @@ Every .hip and .cpp file under csrc/ is compiled with hipcc for
 --offload-arch=gfx950 into _build/, then linked into
 paper_1908_01964_amd/librcscm.so.  Packed-FP32 instructions are disabled
 (-Xclang -target-feature -Xclang -packed-fp32-ops) for all device code.
+Then the plain-C ABI client of the tests (tests/c/abi_run.c) is built
+against the library.
 """
 import argparse
 import concurrent.futures as cf
@@ -60,7 +62,29 @@ def build(jobs=None, verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    _build_c_client(verbose)
     return LIB
+
+
+C_CLIENT_SRC = os.path.join(ROOT, "tests", "c", "abi_run.c")
+C_CLIENT = os.path.join(ROOT, "tests", "c", "abi_run")
+
+
+def _build_c_client(verbose):
+    """The plain-C ABI client used by the tests (gcc, C99, linked against librcscm.so)."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc or not os.path.exists(C_CLIENT_SRC):
+        return
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           f"-I{rocm}/include", f"-I{INCLUDE}", C_CLIENT_SRC, "-o", C_CLIENT, f"-L{PKG}",
+           "-lrcscm", f"-L{rocm}/lib", "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/../../paper_1908_01964_amd", f"-Wl,-rpath,{rocm}/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C client build failed\n{r.stdout}\n{r.stderr}")
 
 
 if __name__ == "__main__":

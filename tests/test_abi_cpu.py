@@ -1,6 +1,7 @@
 """C ABI checks that need no GPU: the library loads, exports every declared function,
 and rejects bad arguments on the host before any device work."""
 import ctypes
+import os
 
 import pytest
 
@@ -103,3 +104,23 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(R, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         R.lib()
+
+
+def test_header_is_plain_c99(tmp_path):
+    """include/rcscm.h is a C header: a C99 translation unit using it compiles without warnings."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler on this host")
+    src = tmp_path / "use.c"
+    src.write_text('#include "rcscm.h"\n'
+                   'int main(void) {\n'
+                   '  rcscm_params p;\n'
+                   '  rcscm_default_params(&p);\n'
+                   '  return (int)rcscm_create(0, 1, 1, 2, &p, 0) == 0;\n'
+                   '}\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                        "-fsyntax-only", f"-I{inc}", str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

@@ -1,0 +1,40 @@
+"""The C ABI used from plain C: tests/c/abi_run (built by python -m paper_1908_01964_amd.build)
+allocates its own device buffers with the HIP runtime and calls rcscm_create / rcscm_run /
+rcscm_sync through include/rcscm.h.  Its outputs must equal the Python binding's bitwise and
+the FP64 oracle within the parity tolerance."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from helpers import assert_close, gpu_run, oracle_accel
+from synth import make_problem
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+C_CLIENT = os.path.join(ROOT, "tests", "c", "abi_run")
+
+
+def test_plain_c_client_matches_binding_and_oracle(tmp_path):
+    if not os.path.exists(C_CLIENT):
+        pytest.fail("tests/c/abi_run is not built: run python -m paper_1908_01964_amd.build")
+    I, J, M, K = 8, 700, 4, 9
+    p = make_problem(M, I, J, config=490, spatial="sinc", n_fft=14)
+    np.ascontiguousarray(p.x, np.complex64).tofile(tmp_path / "x.bin")
+    np.ascontiguousarray(p.a, np.complex128).tofile(tmp_path / "a.bin")
+    np.ascontiguousarray(p.Rp, np.complex128).tofile(tmp_path / "Rp.bin")
+    np.ascontiguousarray(p.b, np.complex128).tofile(tmp_path / "b.bin")
+    r = subprocess.run([C_CLIENT, str(tmp_path), str(I), str(J), str(M), str(K)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.stdout, r.stderr)
+    assert "rcscm status 0" in r.stdout
+    got = dict(rh=np.fromfile(tmp_path / "out_rh.bin", np.float32).reshape(I, J),
+               ru=np.fromfile(tmp_path / "out_ru.bin", np.float32).reshape(I, J),
+               lam=np.fromfile(tmp_path / "out_lam.bin", np.float32),
+               s_hat=np.fromfile(tmp_path / "out_shat.bin", np.complex64).reshape(I, J))
+    ref_bind = gpu_run(p, K, fused=True)[0]
+    for k in got:
+        assert np.array_equal(got[k], np.asarray(ref_bind[k]).reshape(got[k].shape)), k
+    assert_close(got, oracle_accel(p, K), what="plain C client")
