@@ -304,6 +304,17 @@ def test_fused_run_vs_oracle(M, J):
     assert_close(out[0], ref, what=f"fused M={M} J={J}")
 
 
+@pytest.mark.parametrize("J", [256, 257, 512, 513, 1024, 1025, 2048, 2049, 4096, 4097, 8192])
+def test_fused_run_class_boundaries(J):
+    """Rows that exactly fill, or overflow by one frame, each workgroup class of the fused launch
+    (256 x 1/2/4/8, 512 x 8, 1024 x 8): the last lane's last bin and the first padded one."""
+    p = make_problem(2, 2, J, config=455, spatial="random")
+    ref = oracle_accel(p, 6)
+    out, ctx, _ = _gpu_run_fused(p, 6)
+    ctx.close()
+    assert_close(out[0], ref, what=f"fused J={J}")
+
+
 def test_fused_run_equals_separate_calls(c0):
     """Same per-bin code and reduction order as init + iterate + extract with 256-lane rows."""
     out_f, ctx, _ = _gpu_run_fused(c0, 20)
