@@ -4,8 +4,10 @@
 // extraction.  HBM traffic per bin: x (8M bytes) read once; tau^ax, sigma^bx,
 // nu, r^h, r^u (28 bytes) and s_hat (8) written once, plus the caller's
 // copies of r^h, r^u.  Wave 0 issues the setup's loads first; the x loads of
-// the first G bins of every lane follow and overlap the setup.  One launch
-// per (M, workgroup size, bins per lane) class.
+// the first G bins of every lane follow and overlap the setup.  When the
+// adjoint needs them, theta_k at the start of every iteration is stored as
+// well (8 bytes per bin and iteration).  One launch per (M, workgroup size,
+// bins per lane) class.
 #include "init_common.h"
 #include "resident_loop.h"
 
