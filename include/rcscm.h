@@ -109,7 +109,7 @@ typedef struct {
                       smallest of 64..1024 holding the row at <= 4 bins per lane),
                       64, 128, 256, 512 or 1024                                      */
   int chunk;       /* bins per workgroup of the STREAM, init, extract and naive
-                      kernels: 0 (1024), 256, 512, 1024 or 2048                      */
+                      kernels: 0 (512), 256, 512, 1024 or 2048                       */
   unsigned flags;  /* RCSCM_FLAG_* */
 } rcscm_params;
 

@@ -313,7 +313,7 @@ static rcscm_status build_tables(rcscm_ctx* c) {
   }
   c->nbins = boff;
   // chunks (row order); the partial slot of a chunk is its index
-  c->chunk = c->p.chunk ? c->p.chunk : 1024;
+  c->chunk = c->p.chunk ? c->p.chunk : 512;
   c->h_chunks.clear();
   for (int r = 0; r < c->nrows; ++r) {
     RowInfo& ri = c->h_rows[r];
@@ -585,9 +585,16 @@ rcscm_status rcscm_init(rcscm_ctx* c, const void* x, const void* a, const void* 
   return RCSCM_OK;
 }
 
+// The MI355X last-level cache (AMD Infinity Cache): 256 MB.
+constexpr double kLastLevelCacheBytes = 256.0 * 1024.0 * 1024.0;
+
 static rcscm_status enqueue_stream_loop(rcscm_ctx* c, int K) {
   hipStream_t s = c->stream;
   const float alpha = (float)c->p.alpha, beta = (float)c->p.beta;
+  // Every launch re-reads the whole per-bin state (tau^ax, sigma^bx, nu, r^h,
+  // r^u: 28 B per bin); whether it stays in the last-level cache between
+  // launches decides how the launch requests it.
+  const bool nu_early = 28.0 * (double)c->nbins <= kLastLevelCacheBytes;
   int cur = c->lam_cur;
   for (int k = 1; k <= K + 1; ++k) {
     const bool finish = k >= 2;
@@ -596,9 +603,9 @@ static rcscm_status enqueue_stream_loop(rcscm_ctx* c, int K) {
     float* lam_new = c->d_lam[cur ^ 1];
     const uint64_t* part_in = finish ? c->d_part[(k - 2) & 1] : nullptr;
     uint64_t* part_out = start ? c->d_part[(k - 1) & 1] : nullptr;
-    launch_accel_stream(s, c->p.lamsum, finish, start, c->nchunks, c->d_chunks, c->d_rows,
-                        c->d_rcf, c->d_tsig, c->d_nu, c->d_rh, c->d_ru, lam_prev, lam_new, part_in,
-                        part_out, alpha, beta, c->chunk, c->d_status);
+    launch_accel_stream(s, c->p.lamsum, finish, start, nu_early, c->nchunks, c->d_chunks,
+                        c->d_rows, c->d_rcf, c->d_tsig, c->d_nu, c->d_rh, c->d_ru, lam_prev,
+                        lam_new, part_in, part_out, alpha, beta, c->chunk, c->d_status);
     RCSCM_HIP(c, hipGetLastError());
     if (finish) cur ^= 1;
   }

@@ -150,12 +150,14 @@ void launch_accel_resident(hipStream_t s, int nt, int bpl, int lamsum, int nrows
                            unsigned* status);
 
 // STREAM schedule: one launch of stage (finish iteration k-1, start iteration k).
+// nu_early: request nu with the rest of a bin's state (for state that stays in
+// the last-level cache between launches).
 void launch_accel_stream(hipStream_t s, int lamsum, bool finish_prev, bool start_next,
-                         int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
-                         const RowConstF* rcf, const float4* tsig, const float* nu, float* rh,
-                         float* ru, const float* lam_prev, float* lam_new,
-                         const uint64_t* part_in, uint64_t* part_out, float alpha, float beta,
-                         int chunk_threads, unsigned* status);
+                         bool nu_early, int nchunks, const ChunkInfo* chunks,
+                         const RowInfo* rows, const RowConstF* rcf, const float4* tsig,
+                         const float* nu, float* rh, float* ru, const float* lam_prev,
+                         float* lam_new, const uint64_t* part_in, uint64_t* part_out,
+                         float alpha, float beta, int chunk_threads, unsigned* status);
 
 void launch_extract(hipStream_t s, int nchunks, const ChunkInfo* chunks, const RowInfo* rows,
                     const RowConstF* rcf, const float4* tsig, const float* rh_in,
