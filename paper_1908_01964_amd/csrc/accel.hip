@@ -18,6 +18,7 @@
 //   (cheap arithmetic) instead of storing its intermediates.  HBM traffic
 //   per launch: 28 bytes read and 8 bytes written per bin.
 #include "resident_loop.h"
+#include "xcd_order.h"
 
 namespace rcscm {
 
@@ -128,28 +129,6 @@ int nt_index(int nt) {
 // ------------------------------------------------------------------ STREAM --
 
 constexpr int kStreamNT = 256;
-
-// Workgroups are dealt to the 8 XCDs of the chip in turn (workgroup w runs on
-// XCD w mod 8), and each XCD has its own L2. Neighbouring chunks share a cache
-// line wherever a row or chunk boundary falls inside one, so chunks are dealt
-// in tiles: the first 8 T workgroups take chunks 0 .. 8T-1 with T consecutive
-// chunks per XCD, the next 8 T the next 8 T chunks, and so on. Only one chunk
-// boundary in T then crosses L2s, while the launch still moves through memory
-// as one compact window. The last, partial group of 8 T chunks is split into 8
-// contiguous runs the same way. The map is a bijection for any XCD count.
-// (Tiles of 16 chunks measured best: one contiguous run per XCD lost 4 % on
-// state streamed from HBM; no remapping lost 1-3 %.)
-constexpr int kXCDs = 8;
-constexpr int kXcdTile = 16;
-__device__ __forceinline__ int xcd_local_chunk(int w, int n) {
-  constexpr int S = kXCDs * kXcdTile;
-  const int base = (w / S) * S;
-  const int m = (n - base) < S ? (n - base) : S;  // chunks in this group
-  const int v = w - base;
-  const int x = v % kXCDs, i = v / kXCDs;
-  const int q = m / kXCDs, r = m % kXCDs;
-  return base + x * q + (x < r ? x : r) + i;
-}
 
 // NU_EARLY: nu is requested together with the rest of the state (one memory
 // round trip instead of two). That pays while the per-bin state stays in the
@@ -283,7 +262,7 @@ __global__ __launch_bounds__(256) void extract_kernel(
     const float* __restrict__ rh_in, const float* __restrict__ ru_in,
     const float* __restrict__ lam_in, float* __restrict__ rh_out, float* __restrict__ ru_out,
     float* __restrict__ lam_out, float2* __restrict__ s_hat) {
-  const ChunkInfo ck = chunks[blockIdx.x];
+  const ChunkInfo ck = chunks[xcd_local_chunk(blockIdx.x, gridDim.x)];
   const RowInfo ri = rows[ck.row];
   const RowConstF rc = rcf[ck.row];
   const float lam = lam_in[ck.row];

@@ -9,6 +9,7 @@
 // nu (float) for its bins plus their initial r^h, r^u.  Memory-bound: 8M
 // bytes read and 28 written per bin.
 #include "init_common.h"
+#include "xcd_order.h"
 
 namespace rcscm {
 
@@ -19,7 +20,7 @@ constexpr int kInitNT = 256;
 template <int M>
 __global__ __launch_bounds__(kInitNT) __attribute__((amdgpu_waves_per_eu(4))) void init_kernel(
     const InitArgs A) {
-  const ChunkInfo ck = A.chunks[blockIdx.x];
+  const ChunkInfo ck = A.chunks[xcd_local_chunk(blockIdx.x, gridDim.x)];
   const int row = ck.row;
   const RowInfo ri = A.rows[row];
   const int t = threadIdx.x;
