@@ -252,8 +252,8 @@ def time_backproject(I, J, M, K, steps, torch):
 
 def load_workload(wid):
     """(I, Js, Ms, K, problems, label) of a named workload."""
-    from synth import CONFIGS, batch_shapes, batch_utterance, config
-    c = CONFIGS[wid]
+    from synth import WORKLOADS, batch_shapes, batch_utterance, config
+    c = WORKLOADS[wid]
     if wid == 2:
         Js, Ms = batch_shapes()
         probs = [batch_utterance(u) for u in range(len(Js))]
@@ -273,9 +273,9 @@ def bench_adjoint(args):
     import torch
 
     from paper_1908_01964_amd import Context, to_device
-    from synth import CONFIGS, config
+    from synth import WORKLOADS, config
     p = config(3, with_truth=True)
-    I, J, M, K = p.I, p.J, p.M, CONFIGS[3]["K"]
+    I, J, M, K = p.I, p.J, p.M, WORKLOADS[3]["K"]
     x, a, Rp, b = to_device(p)
     dev = x.device
     nbins = I * J
@@ -369,7 +369,7 @@ def main():
 
     import numpy as np
 
-    from synth import CONFIGS
+    from synth import WORKLOADS
 
     if args.workload == 3:
         bench_adjoint(args)
@@ -379,7 +379,7 @@ def main():
     if args.workload == 1 and not args.no_cpu_baseline:
         # before any GPU work: the worker processes are started from a process that has not
         # touched the GPU
-        c1 = CONFIGS[1]
+        c1 = WORKLOADS[1]
         cores = min(16, os.cpu_count() or 1)
         cb, ref = cpu_baseline(c1["I"], c1["J"], c1["K"], args.cpu_reps, cores)
 

@@ -230,7 +230,7 @@ rcscm_status rcscm_backward(rcscm_ctx* ctx, const void* x, const void* grad_s_ha
  * (after a small host-to-device copy of the target indices).  Errors: EINVAL
  * (NULL pointers, target out of range); a singular W is reported as ENOTPSD
  * by the next rcscm_sync (rcscm_init and rcscm_run reset the per-row status
- * and judge the a, R', b they receive by their own checks, so call
+ * and check the a, R', b they receive by their own tests, so call
  * rcscm_sync in between to see this error).  The initialisation of r^h from
  * the NMF factors of
  * ILRMA (eq. (21)) is the caller's (pass it to rcscm_init as rh0). */

@@ -1,2 +1,2 @@
 from .workloads import *  # noqa: F401,F403
-from .workloads import SEED, ALPHA, BETA, CONFIGS, Problem, make_problem, config, batch_shapes, batch_utterance  # noqa: F401
+from .workloads import SEED, ALPHA, BETA, WORKLOADS, Problem, make_problem, config, batch_shapes, batch_utterance  # noqa: F401

@@ -221,7 +221,7 @@ def make_bss_problem(M: int, I: int, J: int, *, config: int = 600, target: int =
 
 # --- the five named workloads -------------------------------------------------
 
-CONFIGS = {
+WORKLOADS = {
     0: dict(name="random-M2", M=2, I=257, J=250, K=20, spatial="random"),
     1: dict(name="sinc-M4", M=4, I=513, J=1000, K=20, spatial="sinc"),
     2: dict(name="batch64-ragged", U=64, I=513, K=20, spatial="random",
@@ -233,7 +233,7 @@ CONFIGS = {
 
 def config(cid: int, freqs: Optional[Sequence[int]] = None, with_truth: bool = True) -> Problem:
     """Single-utterance workload ``cid`` in {0, 1, 3, 4} (config 3 reuses config 1's data)."""
-    c = CONFIGS[cid]
+    c = WORKLOADS[cid]
     if cid == 2:
         raise ValueError("config 2 is a batch: use batch_shapes()/batch_utterance()")
     seed_cfg = 1 if cid == 3 else cid
@@ -259,5 +259,5 @@ def batch_utterance(u: int, I: int = 513, freqs=None, cid: int = 2, with_truth: 
     Js, Ms = batch_shapes(U, J_range, M_choices, cid)
     p = make_problem(Ms[u], I, Js[u], config=cid, utterance=u, spatial="random",
                      freqs=freqs, with_truth=with_truth)
-    p.meta.update(K=CONFIGS[2]["K"], name=CONFIGS[2]["name"], cid=cid)
+    p.meta.update(K=WORKLOADS[2]["K"], name=WORKLOADS[2]["name"], cid=cid)
     return p
