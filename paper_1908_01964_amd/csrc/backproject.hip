@@ -12,7 +12,8 @@
 //   rank, (R')^+ = B^{+H} P^{-1} B^+, hence
 //   r^u_0 = (1/M) y^(u)H (R')^+ y^(u) = (1/M) sum_{m != n_h} |y_m|^2 / p_m
 //   lambda_0 = min nonzero eigenvalue of R' = min eigenvalue of the
-//   (M-1) x (M-1) Gram matrix P^{1/2} B^H B P^{1/2} (cyclic complex Jacobi).
+//   (M-1) x (M-1) Gram matrix P^{1/2} B^H B P^{1/2} (multisection on a
+//   positive-definiteness test, one shift per lane).
 // Launches: bp_power (per chunk: partial sums of |y_m|^2), bp_row (per row:
 // A = W^{-1} by Gauss-Jordan with partial pivoting, a, R', b, lambda_0),
 // bp_ru (per chunk: r^u_0).
@@ -77,64 +78,73 @@ __global__ __launch_bounds__(kBpNT) void bp_power_kernel(const ChunkInfo* __rest
 }
 
 // Smallest eigenvalue of a Hermitian N x N matrix (N <= 7) by cyclic complex
-// Jacobi rotations, run by one lane on a copy held in registers (every index
-// is a compile-time constant).  Each rotation first makes H[p][q] real with a
-// phase on row/column q, then applies the real rotation that zeroes it.
+// True when G - s I is positive definite: every pivot of its LDL^H
+// factorisation (no square roots; unit lower L) is positive. For a positive
+// definite matrix the factorisation is backward stable, so the answer is
+// exact up to rounding of order eps |G| at the boundary s = lambda_min.
 template <int N>
-__device__ double jacobi_min_eig(const double2 (*G)[MAXM]) {
-  double2 H[N][N];
+__device__ __forceinline__ bool shifted_pd(const double2 (&G)[N][N], double s) {
+  double2 L[N][N];
+  double d[N];
 #pragma unroll
-  for (int p = 0; p < N; ++p)
+  for (int k = 0; k < N; ++k) {
+    double dk = G[k][k].x - s;
 #pragma unroll
-    for (int q = 0; q < N; ++q) H[p][q] = G[p][q];
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    double off = 0.0, dia = 0.0;
+    for (int j = 0; j < k; ++j) dk -= d[j] * (L[k][j].x * L[k][j].x + L[k][j].y * L[k][j].y);
+    if (!(dk > 0.0)) return false;
+    d[k] = dk;
+    const double inv = 1.0 / dk;
 #pragma unroll
-    for (int p = 0; p < N; ++p) {
-      dia += H[p][p].x * H[p][p].x;
+    for (int i = k + 1; i < N; ++i) {
+      double2 v = G[i][k];
 #pragma unroll
-      for (int q = p + 1; q < N; ++q) off += H[p][q].x * H[p][q].x + H[p][q].y * H[p][q].y;
+      for (int j = 0; j < k; ++j) {
+        const double2 u = zmul(L[i][j], zconj(L[k][j]));  // L_ij conj(L_kj) d_j
+        v.x -= u.x * d[j];
+        v.y -= u.y * d[j];
+      }
+      L[i][k] = make_double2(v.x * inv, v.y * inv);
     }
-    if (off <= 1e-30 * dia) break;
+  }
+  return true;
+}
+
+// Smallest eigenvalue of the N x N Hermitian positive semidefinite G, by
+// multisection over the 64 lanes of the wave (all of them must call it):
+// G - s I is positive definite exactly when s < lambda_min. The bracket starts
+// at [0, min_k G_kk] (no diagonal entry of a Hermitian matrix lies below its
+// smallest eigenvalue); in each round lane l tests
+// s_l = lo + (hi - lo)(l + 1)/65, and the first lane whose test fails gives
+// the bracket 65 times narrower.
+template <int N>
+__device__ double min_eig_multisection(const double2 (*Gs)[MAXM]) {
+  if constexpr (N == 1) {
+    return Gs[0][0].x;
+  } else {
+    double2 G[N][N];
 #pragma unroll
     for (int p = 0; p < N; ++p)
 #pragma unroll
-      for (int q = p + 1; q < N; ++q) {
-        const double2 apq = H[p][q];
-        const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
-        if (mag < 1e-300) continue;
-        const double2 ph = make_double2(apq.x / mag, apq.y / mag);
+      for (int q = 0; q < N; ++q) G[p][q] = Gs[p][q];
+    double lo = 0.0, hi = G[0][0].x;
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-          if (r == q) continue;
-          H[r][q] = zmul(H[r][q], zconj(ph));
-          H[q][r] = zconj(H[r][q]);
-        }
-        const double a = H[p][p].x, bq = H[q][q].x;
-        const double th = (bq - a) / (2.0 * mag);
-        const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-        const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          if (r == p || r == q) continue;
-          const double2 rp = H[r][p], rq = H[r][q];
-          const double2 np_ = make_double2(cs * rp.x - sn * rq.x, cs * rp.y - sn * rq.y);
-          const double2 nq_ = make_double2(sn * rp.x + cs * rq.x, sn * rp.y + cs * rq.y);
-          H[r][p] = np_;
-          H[p][r] = zconj(np_);
-          H[r][q] = nq_;
-          H[q][r] = zconj(nq_);
-        }
-        H[p][p] = make_double2(a - tt * mag, 0.0);
-        H[q][q] = make_double2(bq + tt * mag, 0.0);
-        H[p][q] = make_double2(0.0, 0.0);
-        H[q][p] = make_double2(0.0, 0.0);
+    for (int k = 1; k < N; ++k) hi = fmin(hi, G[k][k].x);
+    if (!(hi > 0.0)) return hi;
+    const int lane = threadIdx.x & 63;
+    for (int round = 0; round < 16 && hi - lo > 1e-10 * hi; ++round) {
+      const double w = (hi - lo) * (1.0 / 65.0);
+      const bool pd = shifted_pd<N>(G, lo + w * (double)(lane + 1));
+      const unsigned long long fail = __ballot(!pd);
+      if (fail == 0ull) {  // every shift lies below lambda_min
+        lo = lo + w * 64.0;
+      } else {
+        const int f = __ffsll(fail) - 1;  // first shift at or above lambda_min
+        hi = lo + w * (double)(f + 1);
+        lo = lo + w * (double)f;
       }
+    }
+    return 0.5 * (lo + hi);
   }
-  double mn = H[0][0].x;
-#pragma unroll
-  for (int p = 1; p < N; ++p) mn = fmin(mn, H[p][p].x);
-  return mn;
 }
 
 template <int M>
@@ -260,7 +270,8 @@ __global__ __launch_bounds__(64) void bp_row_kernel(const int* __restrict__ row_
       G[k][l] = make_double2(w * s.x, w * s.y);
     }
     wave_sync();
-    if (t == 0) lam0_out[row] = (float)jacobi_min_eig<M - 1>(G);
+    const double lmin = min_eig_multisection<M - 1>(G);
+    if (t == 0) lam0_out[row] = (float)lmin;
   }
   if (t == 0 && sflag) atomicOr(status + row, sflag);
 }
