@@ -14,9 +14,11 @@
 //   lambda_0 = min nonzero eigenvalue of R' = min eigenvalue of the
 //   (M-1) x (M-1) Gram matrix P^{1/2} B^H B P^{1/2} (multisection on a
 //   positive-definiteness test, one shift per lane).
-// Launches: bp_power (per chunk: partial sums of |y_m|^2), bp_row (per row:
-// A = W^{-1} by Gauss-Jordan with partial pivoting, a, R', b, lambda_0),
-// bp_ru (per chunk: r^u_0).
+// Launches: for M <= kBpFusedMaxM and rows of up to kBpFusedMaxJ frames one
+// bp_fused per row (all of the below in one workgroup); otherwise bp_power
+// (per chunk: partial sums of |y_m|^2), bp_row (per row: A = W^{-1} by
+// Gauss-Jordan with partial pivoting, a, R', b, lambda_0) and bp_ru (per
+// chunk: r^u_0).
 #include "accel_common.h"
 #include "small_linalg.h"
 
@@ -147,39 +149,30 @@ __device__ double min_eig_multisection(const double2 (*Gs)[MAXM]) {
   }
 }
 
+// LDS of the per-row step.
 template <int M>
-__global__ __launch_bounds__(64) void bp_row_kernel(const int* __restrict__ row_list,
-                                                    const RowInfo* __restrict__ rows,
-                                                    const double2* __restrict__ W,
-                                                    const int* __restrict__ target,
-                                                    const double* __restrict__ part,
-                                                    double2* __restrict__ a_out,
-                                                    double2* __restrict__ rp_out,
-                                                    double2* __restrict__ b_out,
-                                                    double* __restrict__ p_out,
-                                                    float* __restrict__ lam0_out,
-                                                    unsigned* __restrict__ status) {
-  const int row = row_list[blockIdx.x];
-  const RowInfo ri = rows[row];
-  const int t = threadIdx.x;
+struct BpRowLDS {
+  double2 aug[M][2 * M];
+  double sp[M];  // source powers p_m, set by the caller
+  int spiv;
+  double2 G[MAXM][MAXM];
+  unsigned sflag;  // cleared by the caller
+};
+
+// The per-row step, run by the 64 lanes of one wave once S.sp holds the
+// source powers: A = W^{-1} by Gauss-Jordan with partial pivoting, then a, R',
+// b and lambda_0.
+template <int M>
+__device__ void bp_row_wave(BpRowLDS<M>& S, int row, const RowInfo& ri,
+                            const double2* __restrict__ W, int nh, double2* __restrict__ a_out,
+                            double2* __restrict__ rp_out, double2* __restrict__ b_out,
+                            float* __restrict__ lam0_out, unsigned* __restrict__ status) {
+  const int t = threadIdx.x & 63;
   const int i = t / M, j = t % M;
   const bool ent = t < M * M;
-  const int nh = target[row];
-  __shared__ double2 aug[M][2 * M];
-  __shared__ double sp[M];
-  __shared__ int spiv;
-  __shared__ double2 G[MAXM][MAXM];
-  __shared__ unsigned sflag;
-  if (t == 0) sflag = 0u;
-  if (t < M) {  // p_m = mean_j |y_m|^2
-    double s = 0.0;
-    for (int k = 0; k < ri.nparts; ++k) s += part[(long long)(ri.part_off + k) * MAXM + t];
-    sp[t] = s / (double)ri.J;
-    p_out[(long long)row * MAXM + t] = sp[t];
-  }
   if (ent) {
-    aug[i][j] = W[ri.rp_off + t];
-    aug[i][M + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    S.aug[i][j] = W[ri.rp_off + t];
+    S.aug[i][M + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   wave_sync();
   // Gauss-Jordan with partial pivoting: aug = [W | I] -> [I | W^{-1}]
@@ -188,60 +181,60 @@ __global__ __launch_bounds__(64) void bp_row_kernel(const int* __restrict__ row_
       int best = k;
       double bm = -1.0;
       for (int r = k; r < M; ++r) {
-        const double m2 = aug[r][k].x * aug[r][k].x + aug[r][k].y * aug[r][k].y;
+        const double m2 = S.aug[r][k].x * S.aug[r][k].x + S.aug[r][k].y * S.aug[r][k].y;
         if (m2 > bm) {
           bm = m2;
           best = r;
         }
       }
-      if (!(bm > 0.0)) sflag |= ST_NOT_PSD;  // singular demixing matrix
-      spiv = best;
+      if (!(bm > 0.0)) S.sflag |= ST_NOT_PSD;  // singular demixing matrix
+      S.spiv = best;
     }
     wave_sync();
-    const int pr = spiv;
+    const int pr = S.spiv;
     if (pr != k && t < 2 * M) {  // swap rows k and pr
-      const double2 tmp = aug[k][t];
-      aug[k][t] = aug[pr][t];
-      aug[pr][t] = tmp;
+      const double2 tmp = S.aug[k][t];
+      S.aug[k][t] = S.aug[pr][t];
+      S.aug[pr][t] = tmp;
     }
     wave_sync();
-    const double2 pv = aug[k][k];
+    const double2 pv = S.aug[k][k];
     const double pm = pv.x * pv.x + pv.y * pv.y;
     const double2 ip = pm > 0.0 ? make_double2(pv.x / pm, -pv.y / pm) : make_double2(0.0, 0.0);
     double2 f = make_double2(0.0, 0.0), r1 = f, r2 = f;
     if (ent) {
-      f = aug[i][k];
-      r1 = aug[k][j];
-      r2 = aug[k][M + j];
+      f = S.aug[i][k];
+      r1 = S.aug[k][j];
+      r2 = S.aug[k][M + j];
     }
     wave_sync();
     if (ent) {
       const double2 n1 = zmul(r1, ip), n2 = zmul(r2, ip);
       if (i == k) {
-        aug[k][j] = n1;
-        aug[k][M + j] = n2;
+        S.aug[k][j] = n1;
+        S.aug[k][M + j] = n2;
       } else {
         const double2 d1 = zmul(f, n1), d2 = zmul(f, n2);
-        aug[i][j] = make_double2(aug[i][j].x - d1.x, aug[i][j].y - d1.y);
-        aug[i][M + j] = make_double2(aug[i][M + j].x - d2.x, aug[i][M + j].y - d2.y);
+        S.aug[i][j] = make_double2(S.aug[i][j].x - d1.x, S.aug[i][j].y - d1.y);
+        S.aug[i][M + j] = make_double2(S.aug[i][M + j].x - d2.x, S.aug[i][M + j].y - d2.y);
       }
     }
     wave_sync();
   }
   // A = W^{-1} = aug[:, M:]; column m of A is aug[.][M + m]
   if (ent) {  // R' = sum_{m != nh} p_m a_m a_m^H
-    double2 s = make_double2(0.0, 0.0);
+    double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (m == nh) continue;
-      const double2 v = zmul(aug[i][M + m], zconj(aug[j][M + m]));
-      s.x += sp[m] * v.x;
-      s.y += sp[m] * v.y;
+      const double2 v = zmul(S.aug[i][M + m], zconj(S.aug[j][M + m]));
+      sum.x += S.sp[m] * v.x;
+      sum.y += S.sp[m] * v.y;
     }
-    rp_out[ri.rp_off + t] = s;
+    rp_out[ri.rp_off + t] = sum;
   }
   if (t < M) {
-    a_out[ri.a_off + t] = aug[t][M + nh];
+    a_out[ri.a_off + t] = S.aug[t][M + nh];
     // b = w_nh / |w_nh|, w_nh = conj of row nh of W
     double nw = 0.0;
 #pragma unroll
@@ -259,21 +252,48 @@ __global__ __launch_bounds__(64) void bp_row_kernel(const int* __restrict__ row_
     if (t < n1 * n1) {
       const int k = t / n1, l = t % n1;
       const int mk = k < nh ? k : k + 1, ml = l < nh ? l : l + 1;
-      double2 s = make_double2(0.0, 0.0);
+      double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        const double2 v = zmulc(aug[r][M + mk], aug[r][M + ml]);
-        s.x += v.x;
-        s.y += v.y;
+        const double2 v = zmulc(S.aug[r][M + mk], S.aug[r][M + ml]);
+        sum.x += v.x;
+        sum.y += v.y;
       }
-      const double w = sqrt(sp[mk] * sp[ml]);
-      G[k][l] = make_double2(w * s.x, w * s.y);
+      const double w = sqrt(S.sp[mk] * S.sp[ml]);
+      S.G[k][l] = make_double2(w * sum.x, w * sum.y);
     }
     wave_sync();
-    const double lmin = min_eig_multisection<M - 1>(G);
+    const double lmin = min_eig_multisection<M - 1>(S.G);
     if (t == 0) lam0_out[row] = (float)lmin;
   }
-  if (t == 0 && sflag) atomicOr(status + row, sflag);
+  wave_sync();
+  if (t == 0 && S.sflag) atomicOr(status + row, S.sflag);
+}
+
+template <int M>
+__global__ __launch_bounds__(64) void bp_row_kernel(const int* __restrict__ row_list,
+                                                    const RowInfo* __restrict__ rows,
+                                                    const double2* __restrict__ W,
+                                                    const int* __restrict__ target,
+                                                    const double* __restrict__ part,
+                                                    double2* __restrict__ a_out,
+                                                    double2* __restrict__ rp_out,
+                                                    double2* __restrict__ b_out,
+                                                    double* __restrict__ p_out,
+                                                    float* __restrict__ lam0_out,
+                                                    unsigned* __restrict__ status) {
+  const int row = row_list[blockIdx.x];
+  const RowInfo ri = rows[row];
+  const int t = threadIdx.x;
+  __shared__ BpRowLDS<M> S;
+  if (t == 0) S.sflag = 0u;
+  if (t < M) {  // p_m = mean_j |y_m|^2
+    double sum = 0.0;
+    for (int k = 0; k < ri.nparts; ++k) sum += part[(long long)(ri.part_off + k) * MAXM + t];
+    S.sp[t] = sum / (double)ri.J;
+    p_out[(long long)row * MAXM + t] = S.sp[t];
+  }
+  bp_row_wave<M>(S, row, ri, W, target[row], a_out, rp_out, b_out, lam0_out, status);
 }
 
 template <int M>
@@ -321,6 +341,96 @@ __global__ __launch_bounds__(kBpNT) void bp_ru_kernel(const ChunkInfo* __restric
   }
 }
 
+// The whole back-projection of one row in one workgroup (rows of up to
+// kBpFusedMaxJ frames): the source powers over the row's frames, then wave 0
+// runs the per-row step while every wave forms r^u_0 from a second pass over
+// the row's x (which the first pass left in L2; the second pass needs only W
+// and 1/p_m, so it does not wait for wave 0).
+template <int M>
+__global__ __launch_bounds__(kBpNT) void bp_fused_kernel(
+    const int* __restrict__ row_list, const RowInfo* __restrict__ rows,
+    const float2* __restrict__ x, const double2* __restrict__ W, const int* __restrict__ target,
+    double2* __restrict__ a_out, double2* __restrict__ rp_out, double2* __restrict__ b_out,
+    double* __restrict__ p_out, float* __restrict__ ru0, float* __restrict__ lam0_out,
+    unsigned* __restrict__ status) {
+  const int row = row_list[blockIdx.x];
+  const RowInfo ri = rows[row];
+  const int t = threadIdx.x;
+  const int nh = target[row];
+  __shared__ double2 sW[M][M];
+  __shared__ double red[M][kBpNT / 64];
+  __shared__ double sip[M];
+  __shared__ BpRowLDS<M> S;
+  if (t < M * M) sW[t / M][t % M] = W[ri.rp_off + t];
+  if (t == 0) S.sflag = 0u;
+  __syncthreads();
+  double acc[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) acc[m] = 0.0;
+  for (int jj = t; jj < ri.J; jj += kBpNT) {  // p_m: sum over frames of |y_m|^2
+    const float2* xp = x + ri.x_off + (long long)jj * M;
+    double xr[M], xi[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      const float2 v = xp[n];
+      xr[n] = v.x;
+      xi[n] = v.y;
+    }
+    asm volatile("" ::: "memory");  // keep W in LDS (re-read per bin)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int n = 0; n < M; ++n) {
+        yr = fma(sW[m][n].x, xr[n], fma(-sW[m][n].y, xi[n], yr));
+        yi = fma(sW[m][n].x, xi[n], fma(sW[m][n].y, xr[n], yi));
+      }
+      acc[m] = fma(yr, yr, fma(yi, yi, acc[m]));
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double w = wave_sum_d(acc[m]);
+    if ((t & 63) == 0) red[m][t >> 6] = w;
+  }
+  __syncthreads();
+  if (t < M) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBpNT / 64; ++w) sum += red[t][w];
+    const double pm = sum / (double)ri.J;
+    S.sp[t] = pm;
+    p_out[(long long)row * MAXM + t] = pm;
+    sip[t] = (t != nh && pm > 0.0) ? 1.0 / pm : 0.0;
+  }
+  __syncthreads();
+  if (t < 64) bp_row_wave<M>(S, row, ri, W, nh, a_out, rp_out, b_out, lam0_out, status);
+  if (ru0 == nullptr) return;
+  for (int jj = t; jj < ri.J; jj += kBpNT) {  // r^u_0 = (1/M) sum_{m != n_h} |y_m|^2 / p_m
+    const float2* xp = x + ri.x_off + (long long)jj * M;
+    double xr[M], xi[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      const float2 v = xp[n];
+      xr[n] = v.x;
+      xi[n] = v.y;
+    }
+    asm volatile("" ::: "memory");
+    double e = 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int n = 0; n < M; ++n) {
+        yr = fma(sW[m][n].x, xr[n], fma(-sW[m][n].y, xi[n], yr));
+        yi = fma(sW[m][n].x, xi[n], fma(sW[m][n].y, xr[n], yi));
+      }
+      e = fma(fma(yr, yr, yi * yi), sip[m], e);
+    }
+    ru0[ri.bin_off + jj] = (float)(e / (double)M);
+  }
+}
+
 }  // namespace
 
 void launch_backproject(hipStream_t s, int M, int nchunks_m, const ChunkInfo* chunks_m,
@@ -341,6 +451,9 @@ void launch_backproject(hipStream_t s, int M, int nchunks_m, const ChunkInfo* ch
     if (stage == 2 && nchunks_m > 0 && ru0 != nullptr)                                         \
       hipLaunchKernelGGL(bp_ru_kernel<MM>, dim3(nchunks_m), dim3(kBpNT), 0, s, chunks_m, rows, \
                          x, W, target, p, ru0);                                                \
+    if (stage == 3 && nrows_m > 0)                                                             \
+      hipLaunchKernelGGL(bp_fused_kernel<MM>, dim3(nrows_m), dim3(kBpNT), 0, s, rows_m_list,    \
+                         rows, x, W, target, a_out, rp_out, b_out, p, ru0, lam0, status);       \
     break;
     RCSCM_BP(2)
     RCSCM_BP(3)

@@ -837,11 +837,16 @@ rcscm_status rcscm_backproject(rcscm_ctx* c, const void* x, const void* W, const
                                 hipMemcpyHostToDevice, s));
     RCSCM_HIP(c, hipStreamSynchronize(s));  // the host vector may change on the next call
   }
-  for (int stage = 0; stage < 3; ++stage)
+  // one fused launch per microphone count of at most kBpFusedMaxM whose rows
+  // are all short enough, the three chunked stages for the others
+  int maxJ[RCSCM_MAX_M + 1] = {0};
+  for (const RowInfo& r : c->h_rows) maxJ[r.M] = r.J > maxJ[r.M] ? r.J : maxJ[r.M];
+  for (int stage : {3, 0, 1, 2})
     for (int m = 2; m <= RCSCM_MAX_M; ++m) {
       const auto cr = c->m_range[m];
       const auto rr = c->mrow_range[m];
-      if (rr.second == 0) continue;
+      const bool fused = m <= kBpFusedMaxM && maxJ[m] <= kBpFusedMaxJ;
+      if (rr.second == 0 || (stage == 3) != fused) continue;
       launch_backproject(s, m, cr.second, c->d_chunks_m + cr.first, rr.second,
                          c->d_rows_m + rr.first, c->d_rows, static_cast<const float2*>(x),
                          static_cast<const double2*>(W), c->d_bp_target, c->d_bp_part, c->d_bp_p,

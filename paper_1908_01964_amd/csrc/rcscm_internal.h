@@ -186,8 +186,14 @@ void launch_first_stage(hipStream_t s, int M, int bpl, int nrows, const int* row
                         const float2* x, float* rh, float* ru, float* lam, float alpha,
                         float beta, int K, unsigned* status);
 
-// Back-projection (eq. (11)) and initialisation (eqs. (22), (23)); stage 0:
-// powers p_m per chunk, stage 1: per row (a, R', b, lambda_0), stage 2: r^u_0.
+// Back-projection (eq. (11)) and initialisation (eqs. (22), (23)); stage 3:
+// all of it in one workgroup per row (M <= kBpFusedMaxM and rows of at most
+// kBpFusedMaxJ frames); otherwise stage 0: powers p_m per chunk, stage 1: per
+// row (a, R', b, lambda_0), stage 2: r^u_0. Above M = 5 the per-row step's
+// registers leave room for only two 256-lane workgroups per CU, and the
+// chunked launches measured faster (I = 513, J = 1000, M = 8).
+constexpr int kBpFusedMaxJ = 8192;
+constexpr int kBpFusedMaxM = 5;
 void launch_backproject(hipStream_t s, int M, int nchunks_m, const ChunkInfo* chunks_m,
                         int nrows_m, const int* rows_m_list, const RowInfo* rows, const float2* x,
                         const double2* W, const int* target, double* part, double* p,

@@ -52,10 +52,13 @@ def _check(d, g):
     assert nrel(g["lam0"], o_bp.lam_init(Rp)) < 1e-6
 
 
-@pytest.mark.parametrize("M,target,perturb", [(2, 0, 0.0), (3, 2, 0.2), (4, 1, 0.3),
-                                              (6, 0, 0.1), (8, 5, 0.3)])
-def test_backproject_vs_oracle(M, target, perturb):
-    d = make_bss_problem(M, 5, 300, config=700 + M, target=target, perturb=perturb)
+@pytest.mark.parametrize("M,target,perturb,J", [(2, 0, 0.0, 300), (3, 2, 0.2, 300),
+                                                (4, 1, 0.3, 300), (6, 0, 0.1, 300),
+                                                (8, 5, 0.3, 300), (3, 1, 0.2, 9000)])
+def test_backproject_vs_oracle(M, target, perturb, J):
+    """M <= 5 with rows of up to 8192 frames takes the one-workgroup-per-row launch; M >= 6
+    and the 9000-frame case take the three chunked launches."""
+    d = make_bss_problem(M, 5, J, config=700 + M, target=target, perturb=perturb)
     _check(d, _gpu_bp([d], 5)[0])
 
 
@@ -63,6 +66,15 @@ def test_backproject_ragged_batch():
     ds = [make_bss_problem(m, 4, j, config=720 + u, target=t, perturb=0.2)
           for u, (m, j, t) in enumerate([(2, 70, 1), (5, 1100, 3), (4, 33, 0)])]
     for d, g in zip(ds, _gpu_bp(ds, 4)):
+        _check(d, g)
+
+
+def test_backproject_batch_mixing_fused_and_chunked_classes():
+    """One microphone count with a row over 8192 frames (chunked launches), another with short
+    rows (one workgroup per row), in the same call."""
+    ds = [make_bss_problem(m, 3, j, config=740 + u, target=t, perturb=0.2)
+          for u, (m, j, t) in enumerate([(3, 8500, 1), (4, 120, 2), (3, 40, 0)])]
+    for d, g in zip(ds, _gpu_bp(ds, 3)):
         _check(d, g)
 
 
