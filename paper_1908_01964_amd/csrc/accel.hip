@@ -130,10 +130,35 @@ int nt_index(int nt) {
 
 constexpr int kStreamNT = 256;
 
-// NU_EARLY: nu is requested together with the rest of the state (one memory
-// round trip instead of two). That pays while the per-bin state stays in the
-// last-level cache between launches; when it streams from HBM the extra
-// concurrent stream costs more than the round trip it saves.
+// Accesses to the per-bin state. NTMP marks them non-temporal (streamed past
+// the caches), for state that does not stay in the last-level cache between
+// launches anyway.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <bool NTMP>
+__device__ __forceinline__ float4 ld_state(const float4* p) {
+  if constexpr (NTMP) {
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    return *p;
+  }
+}
+template <bool NTMP>
+__device__ __forceinline__ float ld_state(const float* p) {
+  if constexpr (NTMP) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NTMP>
+__device__ __forceinline__ void st_state(float* p, float v) {
+  if constexpr (NTMP) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// NU_EARLY: the state stays in the last-level cache between launches. nu is
+// then requested together with the rest of the state (one memory round trip
+// instead of two). Otherwise the state streams from HBM: nu is requested after
+// the frame sum (a fourth concurrent stream cost more than the round trip it
+// saves), and all state accesses are non-temporal.
 template <int BPL, int LS, bool FINISH, bool START, bool NU_EARLY>
 __global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
     const ChunkInfo* __restrict__ chunks, const RowInfo* __restrict__ rows,
@@ -159,9 +184,9 @@ __global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
   for (int q = 0; q < BPL; ++q) {
     const int j = t + q * kStreamNT;
     if (j < len) {
-      ts[q] = tsig[base + j];
-      vrh[q] = rh[base + j];
-      vru[q] = ru[base + j];
+      ts[q] = ld_state<!NU_EARLY>(tsig + base + j);
+      vrh[q] = ld_state<!NU_EARLY>(rh + base + j);
+      vru[q] = ld_state<!NU_EARLY>(ru + base + j);
       vnu[q] = (FINISH && NU_EARLY) ? nu[base + j] : 0.f;
     } else {
       ts[q] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -184,13 +209,13 @@ __global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       const int j = t + q * kStreamNT;
-      if (!NU_EARLY && j < len) vnu[q] = nu[base + j];
+      if (!NU_EARLY && j < len) vnu[q] = ld_state<true>(nu + base + j);
       const PhaseA A = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
       vrh[q] = A.rh_new;
       vru[q] = phase_b(ts[q], vnu[q] * rc.invM, A, rc, Ln);
       if (j < len) {
-        rh[base + j] = vrh[q];
-        ru[base + j] = vru[q];
+        st_state<!NU_EARLY>(rh + base + j, vrh[q]);
+        st_state<!NU_EARLY>(ru + base + j, vru[q]);
         bad = bad || !isfinite(vrh[q]) || !isfinite(vru[q]);
       }
     }
