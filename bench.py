@@ -363,7 +363,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the estimation is independent per frequency row and "
-              "this build runs on a single MI355X (see DESIGN.md for how rows would shard). "
+              "the library runs on one MI355X (rows would be sharded by frequency across GPUs). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
