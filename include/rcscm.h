@@ -95,6 +95,9 @@ typedef enum { RCSCM_LAMSUM_F64 = 0, RCSCM_LAMSUM_KAHAN32 = 1 } rcscm_lamsum;
 
 #define RCSCM_FLAG_GRAPH       1u  /* capture the STREAM K loop in a hipGraph      */
 #define RCSCM_FLAG_CHECKPOINT  2u  /* keep theta_k per iteration for rcscm_backward */
+#define RCSCM_FLAG_RUN_ONLY    4u  /* rcscm_run stores its results in the caller's
+                                      arrays only and keeps no state (see rcscm_run);
+                                      not with RCSCM_FLAG_CHECKPOINT                */
 
 typedef struct {
   double alpha;    /* inverse-gamma shape; default 1.1 (Table 2); needs alpha+2 > 0 */
@@ -179,7 +182,12 @@ rcscm_status rcscm_extract(rcscm_ctx* ctx, float* rh, float* ru, float* lam, voi
  * event records/waits only); with several classes make one uncaptured call
  * first, which creates the auxiliary streams.  Leaves the
  * context in the same state as the three calls (iterate/extract/objective
- * may follow).  Asynchronous. */
+ * may follow), except with RCSCM_FLAG_RUN_ONLY: then the fused launch writes
+ * only the outputs (r^h, r^u, lambda, s_hat: 16 bytes per bin and 4 per row,
+ * plus the 8 M bytes per bin it reads), stores no per-bin state in the
+ * workspace (28 bytes per bin less), and iterate, extract, get_state,
+ * objective and backward return ESTATE until the next init (rcscm_sync still
+ * reports the run's data errors).  Asynchronous. */
 rcscm_status rcscm_run(rcscm_ctx* ctx, const void* x, const void* a, const void* Rp,
                        const void* b, const float* rh0, const float* ru0, const float* lam0,
                        int K, float* rh, float* ru, float* lam, void* s_hat);
@@ -187,6 +195,15 @@ rcscm_status rcscm_run(rcscm_ctx* ctx, const void* x, const void* a, const void*
 /* Replaces the state (device arrays in batch layout; none may be NULL).
  * Async.  Used to resume from a saved state. */
 rcscm_status rcscm_set_state(rcscm_ctx* ctx, const float* rh, const float* ru, const float* lam);
+
+/* Copies the current state theta = {r^h, r^u, lambda} (Sec. II-B-2) into
+ * caller-owned device arrays rh, ru (float, batch layout [..][I][J_u]) and lam
+ * (float [U][I]); none may be NULL.  The copy is bitwise the state the next
+ * rcscm_iterate starts from, so rcscm_set_state with these arrays on a context
+ * initialised with the same inputs resumes exactly.  Async (device-to-device
+ * copies on the context's stream).  Errors: EINVAL (NULL), ESTATE before init
+ * or after a RCSCM_FLAG_RUN_ONLY run. */
+rcscm_status rcscm_get_state(rcscm_ctx* ctx, float* rh, float* ru, float* lam);
 
 /* Waits for the context's stream and returns the first data error recorded
  * by a kernel since init (see rcscm_status), or OK. */
@@ -244,12 +261,39 @@ void rcscm_destroy(rcscm_ctx* ctx);
  * be NULL for errors from create). */
 const char* rcscm_last_error(const rcscm_ctx* ctx);
 
-/* Bytes of device workspace a context of this shape allocates. */
+/* Bytes of device workspace rcscm_create / rcscm_create_batch allocate for
+ * this shape and params (params may be NULL: defaults); 0 for arguments
+ * create would reject.  Allocated later, on first use, and not counted:
+ * checkpoints (RCSCM_FLAG_CHECKPOINT) at the first iterate(K) or run(K),
+ * 8 K bytes per bin plus 4 K bytes per row, regrown for a larger K; the
+ * back-projection's scratch at the first rcscm_backproject, 64 bytes per
+ * chunk plus 68 bytes per row. */
 size_t rcscm_workspace_bytes(int U, int I, const int* J, const int* M, const rcscm_params* params);
 
 /* Schedule chosen for the RESIDENT / STREAM loop after create (for tests and
  * the autotuner): writes the schedule, block size and chunk size in use. */
 rcscm_status rcscm_get_schedule(const rcscm_ctx* ctx, int* schedule, int* block, int* chunk);
+
+/* Workgroup classes of rcscm_run's fused launch, for the autotuner.  Every row
+ * runs in one workgroup of nt threads holding bpl frames per lane; the cost of
+ * an iteration does not depend on M (Table 1), so a class is chosen per
+ * (M, row length).  table: HOST array of n entries of 4 ints
+ * (M, j_max, nt, bpl); a row with M_u microphones and J_u frames takes the
+ * first entry with (M == M_u or M == 0), J_u <= j_max and J_u <= nt * bpl.
+ * Rows no entry matches, and every row when n == 0, take the built-in class:
+ * the smallest of 256 x 1/2/4/8, 512 x 8, 1024 x 8 that holds the row.
+ * Supported (nt, bpl): (256, 1/2/4/8), (512, 2/4/8), (1024, 1/2/4/8).  Waits
+ * for the context's streams, then uploads the new row lists (blocks; call
+ * it outside graph capture).  Results do not depend on the class except
+ * through the grouping of the lambda frame sum (rounding).  Errors: EINVAL
+ * (bad entry; nothing is changed). */
+rcscm_status rcscm_set_run_classes(rcscm_ctx* ctx, int n, const int* table);
+
+/* The classes rcscm_run launches for this context: *n is their number, and the
+ * first min(cap, *n) are written to the HOST array table as 5 ints each
+ * (M, nt, bpl, rows, J of the class's first row).  *n == 0: rcscm_run makes
+ * the three calls instead (rows longer than 8192 frames, or another rule). */
+rcscm_status rcscm_get_run_classes(const rcscm_ctx* ctx, int cap, int* table, int* n);
 
 /* Library version (RCSCM_VERSION). */
 int rcscm_version(void);

@@ -7,12 +7,14 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <map>
 #include <string>
 #include <tuple>
 #include <utility>
 #include <vector>
 
+#include "host_internal.h"
 #include "rcscm.h"
 #include "rcscm_internal.h"
 
@@ -24,6 +26,7 @@ thread_local std::string g_create_error;
 
 constexpr int kResBpl[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16};
 constexpr int kMaxResidentJ = 512 * 16;
+constexpr int kDefaultChunk = 512;  // bins per chunk when params.chunk == 0
 
 int round_up_bpl(int need) {
   for (int b : kResBpl)
@@ -48,7 +51,7 @@ struct rcscm_ctx {
   hipStream_t stream = nullptr;
   int nrows = 0;
   long long nbins = 0;
-  int chunk = 1024;
+  int chunk = kDefaultChunk;
   int nchunks = 0;
   int schedule = RCSCM_SCHED_RESIDENT;
   int res_nt = 256;
@@ -69,6 +72,8 @@ struct rcscm_ctx {
     int row0;     // first row of the class
   };
   std::vector<FusedClass> fused_classes;  // rcscm_run (empty: not available)
+  int fused_offset = 0;                     // the fused classes' part of d_row_list
+  std::vector<std::array<int, 4>> run_table;  // (M, j_max, nt, bpl) from rcscm_set_run_classes
 
   Buffers mem;
   RowInfo* d_rows = nullptr;
@@ -103,6 +108,7 @@ struct rcscm_ctx {
   int ck_capacity = 0;
   int ck_K = -1;
   bool inited = false;
+  bool dropped = false;  // the last rcscm_run kept no state (RCSCM_FLAG_RUN_ONLY)
   bool chunk_status_valid = false;  // chunk_status written by the last rcscm_init
   std::string err;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -117,6 +123,12 @@ struct rcscm_ctx {
   rcscm_status fail(rcscm_status s, const std::string& m) {
     err = m;
     return s;
+  }
+  // ESTATE for a call that needs the state: none yet, or dropped by a run-only rcscm_run.
+  rcscm_status no_state(const char* what) {
+    return fail(RCSCM_ESTATE, std::string(what) +
+                                  (dropped ? " after a RCSCM_FLAG_RUN_ONLY run (no state kept)"
+                                           : " before init"));
   }
   template <class T>
   rcscm_status alloc(T** out, size_t count, const char* what) {
@@ -180,6 +192,21 @@ void rcscm_default_params(rcscm_params* p) {
 }
 
 int rcscm_version(void) { return RCSCM_VERSION; }
+
+static rcscm_status validate(int U, int I, const int* J, const int* M, const rcscm_params* p,
+                             std::string* msg);
+
+}  // extern "C"
+
+namespace rcscm {
+rcscm_status validate_args(int U, int I, const int* J, const int* M, const rcscm_params* p,
+                           std::string* msg) {
+  return validate(U, I, J, M, p, msg);
+}
+void set_global_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace rcscm
+
+extern "C" {
 
 static rcscm_status validate(int U, int I, const int* J, const int* M, const rcscm_params* p,
                              std::string* msg) {
@@ -250,8 +277,12 @@ static rcscm_status validate(int U, int I, const int* J, const int* M, const rcs
     *msg = "chunk must be 0, 256, 512, 1024 or 2048";
     return RCSCM_EINVAL;
   }
-  if (p->flags & ~(RCSCM_FLAG_GRAPH | RCSCM_FLAG_CHECKPOINT)) {
+  if (p->flags & ~(RCSCM_FLAG_GRAPH | RCSCM_FLAG_CHECKPOINT | RCSCM_FLAG_RUN_ONLY)) {
     *msg = "unknown flag bits";
+    return RCSCM_EINVAL;
+  }
+  if ((p->flags & RCSCM_FLAG_CHECKPOINT) && (p->flags & RCSCM_FLAG_RUN_ONLY)) {
+    *msg = "RCSCM_FLAG_RUN_ONLY keeps no state, so it excludes RCSCM_FLAG_CHECKPOINT";
     return RCSCM_EINVAL;
   }
   int maxJ = 0;
@@ -286,6 +317,47 @@ static int auto_block(int J) {
   return 1024;
 }
 
+// The fused launch's class of a row: the first entry of the caller's table
+// (rcscm_set_run_classes) that matches, else the built-in choice.
+static bool pick_fused_class(const rcscm_ctx* c, int M, int J, int* nt, int* bpl) {
+  for (const auto& e : c->run_table)
+    if ((e[0] == 0 || e[0] == M) && J <= e[1] && J <= e[2] * e[3]) {
+      *nt = e[2];
+      *bpl = e[3];
+      return true;
+    }
+  return fused_class(J, nt, bpl);
+}
+
+// Groups the rows into the fused launch's classes (M, nt, bpl), appending the
+// rows of each class to *row_list; leaves *out empty when a row fits no class.
+static void group_fused(rcscm_ctx* c, std::vector<int>* row_list,
+                        std::vector<rcscm_ctx::FusedClass>* out) {
+  out->clear();
+  std::map<std::tuple<int, int, int>, std::vector<int>> cls;  // (M, nt, bpl)
+  for (int r = 0; r < c->nrows; ++r) {
+    int nt = 0, bpl = 0;
+    if (!pick_fused_class(c, c->h_rows[r].M, c->h_rows[r].J, &nt, &bpl)) return;
+    cls[std::make_tuple(c->h_rows[r].M, nt, bpl)].push_back(r);
+  }
+  for (auto& kv : cls) {
+    const std::vector<int>& rl = kv.second;
+    bool linear = true;
+    const RowInfo& r0 = c->h_rows[rl[0]];
+    for (size_t k = 1; k < rl.size() && linear; ++k) {
+      const RowInfo& rk = c->h_rows[rl[k]];
+      const long long kk = (long long)k;
+      linear = rl[k] == rl[0] + (int)k && rk.utt == r0.utt && rk.J == r0.J && rk.M == r0.M &&
+               rk.x_off == r0.x_off + kk * r0.J * r0.M && rk.bin_off == r0.bin_off + kk * r0.J &&
+               rk.a_off == r0.a_off + kk * r0.M && rk.rp_off == r0.rp_off + kk * r0.M * r0.M;
+    }
+    out->push_back(rcscm_ctx::FusedClass{std::get<0>(kv.first), std::get<1>(kv.first),
+                                         std::get<2>(kv.first), (int)rl.size(),
+                                         (int)row_list->size(), linear, rl[0]});
+    row_list->insert(row_list->end(), rl.begin(), rl.end());
+  }
+}
+
 static rcscm_status build_tables(rcscm_ctx* c) {
   const int U = c->U, I = c->I;
   c->nrows = U * I;
@@ -313,7 +385,7 @@ static rcscm_status build_tables(rcscm_ctx* c) {
   }
   c->nbins = boff;
   // chunks (row order); the partial slot of a chunk is its index
-  c->chunk = c->p.chunk ? c->p.chunk : 512;
+  c->chunk = c->p.chunk ? c->p.chunk : kDefaultChunk;
   c->h_chunks.clear();
   for (int r = 0; r < c->nrows; ++r) {
     RowInfo& ri = c->h_rows[r];
@@ -391,33 +463,9 @@ static rcscm_status build_tables(rcscm_ctx* c) {
       row_list.insert(row_list.end(), kv.second.begin(), kv.second.end());
     }
   }
-  if (c->p.rule == RCSCM_RULE_ACCEL && maxJ <= kMaxResidentJ) {
-    std::map<std::tuple<int, int, int>, std::vector<int>> cls;  // (M, nt, bpl)
-    bool ok = true;
-    for (int r = 0; r < c->nrows && ok; ++r) {
-      int nt = 0, bpl = 0;
-      ok = fused_class(c->h_rows[r].J, &nt, &bpl);
-      cls[std::make_tuple(c->h_rows[r].M, nt, bpl)].push_back(r);
-    }
-    if (ok)
-      for (auto& kv : cls) {
-        const std::vector<int>& rl = kv.second;
-        bool linear = true;
-        const RowInfo& r0 = c->h_rows[rl[0]];
-        for (size_t k = 1; k < rl.size() && linear; ++k) {
-          const RowInfo& rk = c->h_rows[rl[k]];
-          const long long kk = (long long)k;
-          linear = rl[k] == rl[0] + (int)k && rk.utt == r0.utt && rk.J == r0.J &&
-                   rk.M == r0.M && rk.x_off == r0.x_off + kk * r0.J * r0.M &&
-                   rk.bin_off == r0.bin_off + kk * r0.J && rk.a_off == r0.a_off + kk * r0.M &&
-                   rk.rp_off == r0.rp_off + kk * r0.M * r0.M;
-        }
-        c->fused_classes.push_back(rcscm_ctx::FusedClass{
-            std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), (int)rl.size(),
-            (int)row_list.size(), linear, rl[0]});
-        row_list.insert(row_list.end(), rl.begin(), rl.end());
-      }
-  }
+  c->fused_offset = (int)row_list.size();
+  if (c->p.rule == RCSCM_RULE_ACCEL && maxJ <= kMaxResidentJ)
+    group_fused(c, &row_list, &c->fused_classes);
   if (row_list.empty()) row_list.push_back(0);
   // device copies
   RCSCM_TRY(c->alloc(&c->d_rows, c->nrows, "rows"));
@@ -479,20 +527,40 @@ size_t rcscm_workspace_bytes(int U, int I, const int* J, const int* M,
     rcscm_default_params(&p);
   std::string msg;
   if (validate(U, I, J, M, &p, &msg) != RCSCM_OK) return 0;
+  // mirrors build_tables and alloc_workspace (every buffer holds at least one element)
+  auto n1 = [](long long n) { return n > 0 ? n : 1LL; };
   long long bins = 0, chunks = 0, maxMM = 0;
-  const long long chunk = p.chunk ? p.chunk : 1024;
+  int maxJ = 0;
+  const long long chunk = p.chunk ? p.chunk : kDefaultChunk;
   for (int u = 0; u < U; ++u) {
     bins += (long long)I * J[u];
     chunks += (long long)I * ((J[u] + chunk - 1) / chunk);
     maxMM = M[u] * M[u] > maxMM ? M[u] * M[u] : maxMM;
+    maxJ = J[u] > maxJ ? J[u] : maxJ;
   }
   const long long rows = (long long)U * I;
+  // the row list: RESIDENT classes, then the fused classes (ACCEL); FIRST classes
+  long long row_list = 0;
+  if (p.rule == RCSCM_RULE_ACCEL) {
+    const bool fits = maxJ <= kMaxResidentJ;
+    const bool resident = (p.flags & RCSCM_FLAG_CHECKPOINT) ||
+                          (p.schedule == RCSCM_SCHED_AUTO ? fits
+                                                          : p.schedule == RCSCM_SCHED_RESIDENT);
+    row_list = (resident ? rows : 0) + (fits ? rows : 0);
+  } else if (p.rule == RCSCM_RULE_FIRST) {
+    row_list = rows;
+  }
   size_t b = 0;
-  b += rows * (sizeof(RowInfo) + sizeof(RowConstD) + sizeof(RowConstF) + sizeof(RowSpatialF) +
-               2 * sizeof(float) + sizeof(unsigned) + sizeof(int));
-  b += chunks * (2 * sizeof(ChunkInfo) + 2 * sizeof(uint64_t) + sizeof(double));
-  b += bins * (sizeof(float4) + 3 * sizeof(float));
-  if (p.rule == RCSCM_RULE_NAIVE) b += bins * maxMM * sizeof(float) + 0;
+  // build_tables: rows, chunks, chunks by M, row list, rows by M
+  b += n1(rows) * sizeof(RowInfo) + 2 * n1(chunks) * sizeof(ChunkInfo) + n1(row_list) * sizeof(int) +
+       n1(rows) * sizeof(int);
+  // alloc_workspace: row constants, per-bin state, lambda x 2, partial sums x 2, status words,
+  // objective partials, packed U^ (NAIVE)
+  b += n1(rows) * (sizeof(RowConstD) + sizeof(RowConstF) + sizeof(RowSpatialF));
+  b += n1(bins) * (sizeof(float4) + 3 * sizeof(float));
+  b += 2 * n1(rows) * sizeof(float) + 2 * n1(chunks) * sizeof(uint64_t);
+  b += n1(rows) * sizeof(unsigned) + n1(chunks) * sizeof(unsigned) + n1(chunks) * sizeof(double);
+  if (p.rule == RCSCM_RULE_NAIVE) b += n1(maxMM * bins) * sizeof(float);
   return b;
 }
 
@@ -580,6 +648,7 @@ rcscm_status rcscm_init(rcscm_ctx* c, const void* x, const void* a, const void* 
   }
   c->x_borrowed = static_cast<const float2*>(x);
   c->inited = true;
+  c->dropped = false;
   c->chunk_status_valid = true;
   c->ck_K = -1;
   return RCSCM_OK;
@@ -632,7 +701,7 @@ static rcscm_status ensure_checkpoints(rcscm_ctx* c, int K) {
 rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
   if (!c) return RCSCM_EINVAL;
   if (K < 0) return c->fail(RCSCM_ESHAPE, "K must be >= 0");
-  if (!c->inited) return c->fail(RCSCM_ESTATE, "iterate before init");
+  if (!c->inited) return c->no_state("iterate");
   if (K == 0) return RCSCM_OK;
   hipStream_t s = c->stream;
   const float alpha = (float)c->p.alpha, beta = (float)c->p.beta;
@@ -721,7 +790,7 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
 
 rcscm_status rcscm_extract(rcscm_ctx* c, float* rh, float* ru, float* lam, void* s_hat) {
   if (!c) return RCSCM_EINVAL;
-  if (!c->inited) return c->fail(RCSCM_ESTATE, "extract before init");
+  if (!c->inited) return c->no_state("extract");
   if (!rh && !ru && !lam && !s_hat) return RCSCM_OK;
   launch_extract(c->stream, c->nchunks, c->d_chunks, c->d_rows, c->d_rcf, c->d_tsig, c->d_rh,
                  c->d_ru, c->d_lam[c->lam_cur], rh, ru, lam, static_cast<float2*>(s_hat),
@@ -732,7 +801,7 @@ rcscm_status rcscm_extract(rcscm_ctx* c, float* rh, float* ru, float* lam, void*
 
 rcscm_status rcscm_set_state(rcscm_ctx* c, const float* rh, const float* ru, const float* lam) {
   if (!c) return RCSCM_EINVAL;
-  if (!c->inited) return c->fail(RCSCM_ESTATE, "set_state before init");
+  if (!c->inited) return c->no_state("set_state");
   if (!rh || !ru || !lam) return c->fail(RCSCM_EINVAL, "state arrays must not be NULL");
   hipStream_t s = c->stream;
   RCSCM_HIP(c, hipMemcpyAsync(c->d_rh, rh, sizeof(float) * c->nbins, hipMemcpyDeviceToDevice, s));
@@ -740,6 +809,18 @@ rcscm_status rcscm_set_state(rcscm_ctx* c, const float* rh, const float* ru, con
   RCSCM_HIP(c, hipMemcpyAsync(c->d_lam[c->lam_cur], lam, sizeof(float) * c->nrows,
                               hipMemcpyDeviceToDevice, s));
   c->ck_K = -1;
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_get_state(rcscm_ctx* c, float* rh, float* ru, float* lam) {
+  if (!c) return RCSCM_EINVAL;
+  if (!rh || !ru || !lam) return c->fail(RCSCM_EINVAL, "state arrays must not be NULL");
+  if (!c->inited) return c->no_state("get_state");
+  hipStream_t s = c->stream;
+  RCSCM_HIP(c, hipMemcpyAsync(rh, c->d_rh, sizeof(float) * c->nbins, hipMemcpyDeviceToDevice, s));
+  RCSCM_HIP(c, hipMemcpyAsync(ru, c->d_ru, sizeof(float) * c->nbins, hipMemcpyDeviceToDevice, s));
+  RCSCM_HIP(c, hipMemcpyAsync(lam, c->d_lam[c->lam_cur], sizeof(float) * c->nrows,
+                              hipMemcpyDeviceToDevice, s));
   return RCSCM_OK;
 }
 
@@ -782,7 +863,7 @@ rcscm_status rcscm_sync(rcscm_ctx* c) {
 
 rcscm_status rcscm_objective(rcscm_ctx* c, double* nlp) {
   if (!c || !nlp) return RCSCM_EINVAL;
-  if (!c->inited) return c->fail(RCSCM_ESTATE, "objective before init");
+  if (!c->inited) return c->no_state("objective");
   launch_objective(c->stream, c->nchunks, c->d_chunks, c->d_rows, c->d_rcf, c->d_rcd, c->d_tsig,
                    c->d_nu, c->d_rh, c->d_ru, c->d_lam[c->lam_cur], c->p.alpha, c->p.beta,
                    c->d_objpart);
@@ -800,7 +881,7 @@ rcscm_status rcscm_objective(rcscm_ctx* c, double* nlp) {
 rcscm_status rcscm_backward(rcscm_ctx* c, const void* x, const void* grad_s_hat, void* grad_x,
                             float* grad_rh0, float* grad_lam0) {
   if (!c) return RCSCM_EINVAL;
-  if (!(c->p.flags & RCSCM_FLAG_CHECKPOINT) || c->ck_K < 0)
+  if (!(c->p.flags & RCSCM_FLAG_CHECKPOINT) || c->ck_K < 0 || !c->inited)
     return c->fail(RCSCM_ESTATE, "backward needs a context with checkpoints that was iterated");
   if (!x || !grad_s_hat) return c->fail(RCSCM_EINVAL, "x and grad_s_hat must not be NULL");
   for (const auto& cl : c->res_classes) {
@@ -902,6 +983,7 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
     return rcscm_extract(c, rh, ru, lam, s_hat);
   }
   c->lam_cur = 0;
+  const bool keep = (c->p.flags & RCSCM_FLAG_RUN_ONLY) == 0;  // store the state for later calls
   FusedArgs A;
   A.rows = c->d_rows;
   A.x = static_cast<const float2*>(x);
@@ -914,14 +996,14 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   A.rh_c = c->p.rh0;
   A.ru_c = c->p.ru0;
   A.lam_c = c->p.lam0;
-  A.rcd = c->d_rcd;
-  A.rcf = c->d_rcf;
+  A.rcd = keep ? c->d_rcd : nullptr;
+  A.rcf = keep ? c->d_rcf : nullptr;
   A.rsf = nullptr;  // the fused path serves the accelerated rule only
-  A.tsig = c->d_tsig;
-  A.nu = c->d_nu;
-  A.rh = c->d_rh;
-  A.ru = c->d_ru;
-  A.lam = c->d_lam[c->lam_cur];
+  A.tsig = keep ? c->d_tsig : nullptr;
+  A.nu = keep ? c->d_nu : nullptr;
+  A.rh = keep ? c->d_rh : nullptr;
+  A.ru = keep ? c->d_ru : nullptr;
+  A.lam = keep ? c->d_lam[c->lam_cur] : nullptr;
   A.status = c->d_status;
   A.rh_out = rh;
   A.ru_out = ru;
@@ -982,8 +1064,53 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
     RCSCM_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
   }
   c->x_borrowed = static_cast<const float2*>(x);
-  c->inited = true;
+  c->inited = keep;
+  c->dropped = !keep;
   c->ck_K = ckpt ? K : -1;
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_set_run_classes(rcscm_ctx* c, int n, const int* table) {
+  if (!c) return RCSCM_EINVAL;
+  if (n < 0 || (n > 0 && !table)) return c->fail(RCSCM_EINVAL, "n must be >= 0 and table non-NULL");
+  std::vector<std::array<int, 4>> t;
+  for (int k = 0; k < n; ++k) {
+    const int M = table[4 * k], jmax = table[4 * k + 1], nt = table[4 * k + 2],
+              bpl = table[4 * k + 3];
+    if (!(M == 0 || (M >= 2 && M <= RCSCM_MAX_M)) || jmax < 1 || !fused_supported(nt, bpl))
+      return c->fail(RCSCM_EINVAL,
+                     "run class entry " + std::to_string(k) +
+                         ": M must be 0 or 2..8, j_max >= 1, and (nt, bpl) one of (256, 1/2/4/8), "
+                         "(512, 2/4/8), (1024, 1/2/4/8)");
+    t.push_back({M, jmax, nt, bpl});
+  }
+  c->run_table = t;
+  if (c->fused_classes.empty()) return RCSCM_OK;  // no fused launch for this context
+  std::vector<int> rl;
+  std::vector<rcscm_ctx::FusedClass> cls;
+  group_fused(c, &rl, &cls);
+  if (cls.empty()) return c->fail(RCSCM_EDEVICE, "regrouping the fused classes failed");
+  for (auto& cl : cls) cl.offset += c->fused_offset;
+  // queued runs may still read the row list
+  RCSCM_HIP(c, hipStreamSynchronize(c->stream));
+  for (hipStream_t st : c->aux) RCSCM_HIP(c, hipStreamSynchronize(st));
+  RCSCM_HIP(c, hipMemcpy(c->d_row_list + c->fused_offset, rl.data(), sizeof(int) * rl.size(),
+                         hipMemcpyHostToDevice));
+  c->fused_classes = cls;
+  return RCSCM_OK;
+}
+
+rcscm_status rcscm_get_run_classes(const rcscm_ctx* c, int cap, int* table, int* n) {
+  if (!c || !n || (cap > 0 && !table)) return RCSCM_EINVAL;
+  *n = (int)c->fused_classes.size();
+  for (int k = 0; k < *n && k < cap; ++k) {
+    const auto& cl = c->fused_classes[k];
+    table[5 * k] = cl.M;
+    table[5 * k + 1] = cl.nt;
+    table[5 * k + 2] = cl.bpl;
+    table[5 * k + 3] = cl.count;
+    table[5 * k + 4] = c->h_rows[cl.row0].J;
+  }
   return RCSCM_OK;
 }
 

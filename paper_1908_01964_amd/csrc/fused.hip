@@ -1,9 +1,10 @@
 // rcscm_run: the whole path of one row in one workgroup and one launch -
 // per-row FP64 setup, per-bin FP64 precomputation into registers, K
 // second-stage iterations (Algorithm 2) in registers, Wiener-filter
-// extraction.  HBM traffic per bin: x (8M bytes) read once; tau^ax, sigma^bx,
-// nu, r^h, r^u (28 bytes) and s_hat (8) written once, plus the caller's
-// copies of r^h, r^u.  Wave 0 issues the setup's loads first; the x loads of
+// extraction.  HBM traffic per bin: x (8M bytes) read once; r^h, r^u and
+// s_hat (16) written once to the caller; unless the run keeps no state
+// (null workspace pointers), tau^ax, sigma^bx, nu, r^h, r^u (28 bytes) are
+// also stored for a later iterate/extract/objective/backward.  Wave 0 issues the setup's loads first; the x loads of
 // the first G bins of every lane follow and overlap the setup.  When the
 // adjoint needs them, theta_k at the start of every iteration is stored as
 // well (8 bytes per bin and iteration).  One launch per (M, workgroup size,
@@ -68,8 +69,10 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
     const int j = t + q * NT;
     if (j < J) {
       precompute_bin<M>(xv[q % G], L, inv_taa, ts[q], vnu[q], bad_x);
-      A.tsig[base + j] = ts[q];
-      A.nu[base + j] = vnu[q];
+      if (A.tsig) {  // the state a later iterate/extract/objective/backward reads
+        A.tsig[base + j] = ts[q];
+        A.nu[base + j] = vnu[q];
+      }
       vrh[q] = A.rh0 ? A.rh0[base + j] : A.rh_c;
       vru[q] = A.ru0 ? A.ru0[base + j] : A.ru_c;
       bad_state = bad_state || !(vrh[q] > 0.0f) || !(vru[q] > 0.0f) || !isfinite(vrh[q]) ||
@@ -91,15 +94,17 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   for (int q = 0; q < BPL; ++q) {
     const int j = t + q * NT;
     if (j >= J) continue;
-    A.rh[base + j] = vrh[q];
-    A.ru[base + j] = vru[q];
+    if (A.rh) {
+      A.rh[base + j] = vrh[q];
+      A.ru[base + j] = vru[q];
+    }
     if (A.rh_out) A.rh_out[base + j] = vrh[q];
     if (A.ru_out) A.ru_out[base + j] = vru[q];
     if (A.s_hat) A.s_hat[base + j] = s_hat_of(ts[q], vrh[q], vru[q], Lf);
     bad_state = bad_state || !isfinite(vrh[q]) || !isfinite(vru[q]);
   }
   if (t == 0) {
-    A.lam[row] = lam_fin;
+    if (A.lam) A.lam[row] = lam_fin;
     if (A.lam_out) A.lam_out[row] = lam_fin;
     if (!(lam_fin > 0.0f) || !isfinite(lam_fin)) atomicOr(&cflag, ST_LAM_NONPOS);
   }
@@ -122,12 +127,27 @@ void fused_launch_m(hipStream_t s, int nt, int bpl, int nrows, const FusedArgs& 
   RCSCM_FU(256, 2)
   RCSCM_FU(256, 4)
   RCSCM_FU(256, 8)
+  RCSCM_FU(512, 2)
+  RCSCM_FU(512, 4)
   RCSCM_FU(512, 8)
+  RCSCM_FU(1024, 1)
+  RCSCM_FU(1024, 2)
+  RCSCM_FU(1024, 4)
   RCSCM_FU(1024, 8)
 #undef RCSCM_FU
 }
 
 }  // namespace
+
+// The (workgroup size, bins per lane) pairs the fused launch is instantiated
+// for; the autotuner chooses among them per (M, row length).
+bool fused_supported(int nt, int bpl) {
+  const int cls[11][2] = {{256, 1}, {256, 2},  {256, 4},  {256, 8},  {512, 2}, {512, 4},
+                          {512, 8}, {1024, 1}, {1024, 2}, {1024, 4}, {1024, 8}};
+  for (const auto& c : cls)
+    if (c[0] == nt && c[1] == bpl) return true;
+  return false;
+}
 
 // The smallest class holding the row.  Measured on MI355X: 256 lanes up to
 // 2048 frames, then 512 x 8 (24 % faster than 1024 x 4 at J = 3000), then

@@ -182,7 +182,8 @@ __device__ __forceinline__ RowConstF row_const_f(const SetupLDS<M>& L, const Row
 // or two per thread: Q by threads [0, M*M), R' by [64, 64 + M*M), c, b, a by
 // [128, 128 + M), [160, ...), [192, ...), the scalars by thread 224.  rsf
 // (the float model of the naive rule) may be null.  Also sets the row's
-// initial lambda and its status word.
+// initial lambda and its status word.  With rcd == null (a run that keeps no
+// state) only the status word is stored: rcf and lam are then not read.
 template <int M, int NT>
 __device__ void write_row_constants(const SetupLDS<M>& L, int row, const RowInfo& ri,
                                     RowConstD* __restrict__ rcd, RowConstF* __restrict__ rcf,
@@ -191,6 +192,15 @@ __device__ void write_row_constants(const SetupLDS<M>& L, int row, const RowInfo
                                     unsigned* __restrict__ status) {
   static_assert(NT >= 256 && M * M <= 64 && M <= 32, "thread map of the row constants");
   const int t = threadIdx.x;
+  if (rcd == nullptr) {
+    if (t == 224) {
+      const float l = lam0 ? lam0[row] : lam_c;
+      unsigned f = L.flags;
+      if (!(l > 0.0f) || !isfinite(l)) f |= ST_NONFINITE_STATE;
+      status[row] = f;
+    }
+    return;
+  }
   RowConstD* D = rcd + row;
   RowSpatialF* S = rsf != nullptr ? rsf + row : nullptr;
   if (t < M * M) {

@@ -138,6 +138,7 @@ struct FusedArgs {
   int K;
 };
 bool fused_class(int J, int* nt, int* bpl);
+bool fused_supported(int nt, int bpl);
 void launch_fused(hipStream_t s, int M, int nt, int bpl, int nrows, const FusedArgs& A);
 
 // RESIDENT schedule: rows in row_list (all with J <= nt * bpl).

@@ -25,6 +25,7 @@ SCHEDULES = {"auto": 0, "stream": 1, "resident": 2}
 LAMSUMS = {"f64": 0, "kahan32": 1}
 FLAG_GRAPH = 1
 FLAG_CHECKPOINT = 2
+FLAG_RUN_ONLY = 4
 
 
 class RcscmError(RuntimeError):
@@ -52,6 +53,7 @@ _SIGS = {
     "rcscm_iterate": (_I, [_P, _I]),
     "rcscm_extract": (_I, [_P, _P, _P, _P, _P]),
     "rcscm_set_state": (_I, [_P, _P, _P, _P]),
+    "rcscm_get_state": (_I, [_P, _P, _P, _P]),
     "rcscm_sync": (_I, [_P]),
     "rcscm_objective": (_I, [_P, ctypes.POINTER(ctypes.c_double)]),
     "rcscm_backward": (_I, [_P, _P, _P, _P, _P, _P]),
@@ -62,6 +64,8 @@ _SIGS = {
     "rcscm_get_schedule": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "rcscm_backproject": (_I, [_P, _P, _P, ctypes.POINTER(_I), _P, _P, _P, _P, _P]),
     "rcscm_run": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _I, _P, _P, _P, _P]),
+    "rcscm_set_run_classes": (_I, [_P, _I, ctypes.POINTER(_I)]),
+    "rcscm_get_run_classes": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
 }
 
 _lib = None
@@ -122,7 +126,8 @@ def workspace_bytes(I: int, Js: Sequence[int], Ms: Sequence[int], **kw) -> int:
 
 
 def _params(alpha=1.1, beta=1e-16, rh0=1.0, ru0=1.0, lam0=1.0, rule="accel", schedule="auto",
-            lamsum="f64", block=0, chunk=0, graph=False, checkpoint=False) -> Params:
+            lamsum="f64", block=0, chunk=0, graph=False, checkpoint=False,
+            run_only=False) -> Params:
     p = default_params()
     p.alpha, p.beta = float(alpha), float(beta)
     p.rh0, p.ru0, p.lam0 = float(rh0), float(ru0), float(lam0)
@@ -130,7 +135,8 @@ def _params(alpha=1.1, beta=1e-16, rh0=1.0, ru0=1.0, lam0=1.0, rule="accel", sch
     p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     p.lamsum = LAMSUMS[lamsum] if isinstance(lamsum, str) else int(lamsum)
     p.block, p.chunk = int(block), int(chunk)
-    p.flags = (FLAG_GRAPH if graph else 0) | (FLAG_CHECKPOINT if checkpoint else 0)
+    p.flags = ((FLAG_GRAPH if graph else 0) | (FLAG_CHECKPOINT if checkpoint else 0)
+               | (FLAG_RUN_ONLY if run_only else 0))
     return p
 
 
@@ -142,7 +148,7 @@ class Context:
     """
 
     def __init__(self, I: int, Js: Sequence[int], Ms: Sequence[int], device=None, stream=None,
-                 **params):
+                 run_classes=None, **params):
         self.I, self.Js, self.Ms = int(I), [int(j) for j in Js], [int(m) for m in Ms]
         self.U = len(self.Js)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
@@ -166,6 +172,8 @@ class Context:
         _check(st, None)
         self._h = h
         self._keep = []  # tensors the library borrows (x for the naive rule)
+        if run_classes:
+            self.set_run_classes(run_classes)
 
     @classmethod
     def single(cls, I: int, J: int, M: int, **kw) -> "Context":
@@ -240,6 +248,20 @@ class Context:
         _check(lib().rcscm_set_state(self._h, _ptr(rh), _ptr(ru), _ptr(lam)), self._h)
         return self
 
+    def get_state(self, out=None):
+        """Copies the current state into dict(rh, ru, lam) device tensors (batch layout)."""
+        dev = self.device
+        if out is None:
+            out = dict(rh=torch.empty(self.nbins, dtype=torch.float32, device=dev),
+                       ru=torch.empty(self.nbins, dtype=torch.float32, device=dev),
+                       lam=torch.empty(self.nrows, dtype=torch.float32, device=dev))
+        for k, n in (("rh", self.nbins), ("ru", self.nbins), ("lam", self.nrows)):
+            if out[k].dtype != torch.float32 or out[k].numel() != n:
+                raise ValueError("state arrays must be float32 with the batch sizes")
+        _check(lib().rcscm_get_state(self._h, _ptr(out["rh"]), _ptr(out["ru"]), _ptr(out["lam"])),
+               self._h)
+        return out
+
     def sync(self):
         _check(lib().rcscm_sync(self._h), self._h)
         return self
@@ -287,6 +309,23 @@ class Context:
         _check(lib().rcscm_backproject(self._h, _ptr(x), _ptr(W), T, _ptr(a), _ptr(Rp), _ptr(b),
                                        _ptr(ru0), _ptr(lam0)), self._h)
         return a, Rp, b, ru0, lam0
+
+    def set_run_classes(self, table):
+        """Workgroup classes of run()'s fused launch: entries (M, j_max, nt, bpl); [] = built-in."""
+        flat = [int(v) for e in table for v in e]
+        arr = (ctypes.c_int * max(1, len(flat)))(*flat)
+        _check(lib().rcscm_set_run_classes(self._h, len(table), arr), self._h)
+        return self
+
+    def run_classes(self):
+        """The classes run() launches: list of dict(M, nt, bpl, rows, J)."""
+        n = ctypes.c_int()
+        _check(lib().rcscm_get_run_classes(self._h, 0, None, ctypes.byref(n)), self._h)
+        cap = max(1, n.value)
+        arr = (ctypes.c_int * (5 * cap))()
+        _check(lib().rcscm_get_run_classes(self._h, cap, arr, ctypes.byref(n)), self._h)
+        return [dict(M=arr[5 * k], nt=arr[5 * k + 1], bpl=arr[5 * k + 2], rows=arr[5 * k + 3],
+                     J=arr[5 * k + 4]) for k in range(n.value)]
 
     def schedule(self):
         s, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

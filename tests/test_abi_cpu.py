@@ -53,6 +53,7 @@ def _create(I=4, J=16, M=4, **kw):
     (dict(rule="naive", checkpoint=True), R.EINVAL, "checkpoints"),
     (dict(rule="first", J=5000), R.ESHAPE, "FIRST"),
     (dict(rule=3), R.EINVAL, "rule"),
+    (dict(run_only=True, checkpoint=True), R.EINVAL, "RUN_ONLY"),
 ])
 def test_create_rejects_bad_arguments_on_host(kw, status, msg):
     st, err = _create(**kw)
@@ -78,6 +79,7 @@ def test_null_context_calls():
     assert L.rcscm_extract(None, None, None, None, None) == R.EINVAL
     assert L.rcscm_sync(None) == R.EINVAL
     assert L.rcscm_set_state(None, None, None, None) == R.EINVAL
+    assert L.rcscm_get_state(None, None, None, None) == R.EINVAL
     assert L.rcscm_backward(None, None, None, None, None, None) == R.EINVAL
     v = ctypes.c_double()
     assert L.rcscm_objective(None, ctypes.byref(v)) == R.EINVAL
@@ -93,10 +95,63 @@ def test_workspace_bytes():
     # per bin at least tau/sigma (16) + nu (4) + r^h, r^u (8)
     assert w1 >= 513 * 1000 * 28
     wn = pkg.workspace_bytes(513, [1000], [4], rule="naive")
-    assert wn >= w1 + 513 * 1000 * 16 * 4  # packed U^ (M^2 floats per bin)
+    # packed U^ (M^2 floats per bin); the naive rule has no RESIDENT or fused row lists
+    assert wn >= w1 + 513 * 1000 * 16 * 4 - 2 * 513 * 4
     assert pkg.workspace_bytes(513, [0], [4]) == 0
     wb = pkg.workspace_bytes(8, [100, 300], [2, 6])
     assert wb > pkg.workspace_bytes(8, [100], [2])
+
+
+# Sizes of the library's device records (rcscm_internal.h): RowInfo 4 x 8 + 6 x 4 bytes,
+# ChunkInfo 4 ints, RowConstF 8 floats, RowConstD (R')^+ and R' (64 double2 each), c, b, a
+# (8 double2 each), sigma^ab (double2) and three doubles, RowSpatialF a, b (8 float2 each)
+# and R' (64 float2); RowConstD is padded to the 16-byte alignment of double2.
+_ROWINFO, _CHUNK, _RCF = 56, 16, 32
+_RCD = -(-(2 * 64 * 16 + 3 * 8 * 16 + 16 + 3 * 8) // 16) * 16
+_RSF = 2 * 8 * 8 + 64 * 8
+
+
+def _expected_workspace(I, Js, Ms, rule="accel", chunk=0, schedule="auto", checkpoint=False):
+    """Every buffer rcscm_create allocates, counted from the allocation list: row, chunk,
+    chunk-by-M, row-list and row-by-M tables; three row-constant records; per bin tau^ax,
+    sigma^bx (float4), nu, r^h, r^u; lambda and the chunk partial sums twice; row and chunk
+    status words; objective partials; packed U^ (M^2 floats per bin, naive rule)."""
+    ck = chunk or 512
+    rows = len(Js) * I
+    bins = sum(I * j for j in Js)
+    chunks = sum(I * -(-j // ck) for j in Js)
+    fits = max(Js) <= 8192
+    if rule == "accel":
+        resident = checkpoint or (fits if schedule == "auto" else schedule == "resident")
+        row_list = (rows if resident else 0) + (rows if fits else 0)
+    else:
+        row_list = rows if rule == "first" else 0
+    b = rows * _ROWINFO + 2 * chunks * _CHUNK + max(row_list, 1) * 4 + rows * 4
+    b += rows * (_RCD + _RCF + _RSF) + bins * (16 + 3 * 4)
+    b += 2 * rows * 4 + 2 * chunks * 8 + rows * 4 + chunks * 4 + chunks * 8
+    if rule == "naive":
+        b += max(m * m for m in Ms) * bins * 4
+    return b
+
+
+@pytest.mark.parametrize("I,Js,Ms,kw", [
+    (513, [1000], [4], {}),
+    (513, [1000], [4], dict(chunk=512)),
+    (513, [1000], [4], dict(chunk=1024)),
+    (513, [1000], [4], dict(rule="naive")),
+    (513, [1000], [4], dict(rule="first")),
+    (513, [1000], [4], dict(schedule="stream")),
+    (1025, [8000], [8], dict(checkpoint=True)),
+    (9, [9000], [2], {}),
+    (8, [100, 300, 2049], [2, 6, 3], {}),
+])
+def test_workspace_bytes_counts_every_buffer(I, Js, Ms, kw):
+    assert pkg.workspace_bytes(I, Js, Ms, **kw) == _expected_workspace(I, Js, Ms, **kw)
+
+
+def test_workspace_default_chunk_is_512():
+    assert pkg.workspace_bytes(513, [1000], [4]) == pkg.workspace_bytes(513, [1000], [4], chunk=512)
+    assert pkg.workspace_bytes(513, [1000], [4]) != pkg.workspace_bytes(513, [1000], [4], chunk=1024)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

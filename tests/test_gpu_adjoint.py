@@ -15,7 +15,7 @@ from synth import ALPHA, BETA, config, make_problem
 
 pytestmark = pytest.mark.gpu
 
-TOL_GRAD = 2e-3  # normwise, FP32 forward + adjoint vs FP64
+TOL_GRAD = 1e-4  # normwise, FP32 forward + adjoint vs FP64 (measured <= 1.4e-5)
 
 
 def _gpu_grads(p, K, rh0, lam0, **params):

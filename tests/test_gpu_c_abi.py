@@ -1,7 +1,8 @@
 """The C ABI used from plain C: tests/c/abi_run (built by python -m paper_1908_01964_amd.build)
 allocates its own device buffers with the HIP runtime and calls rcscm_create / rcscm_run /
 rcscm_sync through include/rcscm.h.  Its outputs must equal the Python binding's bitwise and
-the FP64 oracle within the parity tolerance."""
+the FP64 oracle within the parity tolerance; its resume round trip (rcscm_get_state, then
+rcscm_set_state on a second context) must be bit-exact."""
 import os
 import subprocess
 
@@ -30,6 +31,8 @@ def test_plain_c_client_matches_binding_and_oracle(tmp_path):
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, (r.stdout, r.stderr)
     assert "rcscm status 0" in r.stdout
+    # rcscm_get_state equals the run's outputs, and set_state(get_state) resumes bitwise
+    assert "get_state 1" in r.stdout and "resume 1" in r.stdout, r.stdout
     got = dict(rh=np.fromfile(tmp_path / "out_rh.bin", np.float32).reshape(I, J),
                ru=np.fromfile(tmp_path / "out_ru.bin", np.float32).reshape(I, J),
                lam=np.fromfile(tmp_path / "out_lam.bin", np.float32),

@@ -240,6 +240,29 @@ def test_extraction_is_posterior_mean():
             assert abs(sh[i, j] - m) < 1e-12 * max(abs(m), 1e-30)
 
 
+def test_spatial_image_is_posterior_mean_of_the_image():
+    """h_hat = a s_hat is E[a s | x]: (1) a times the posterior mean of s from generic Gaussian
+    conditioning of [s; u; x]; (2) the complement of the posterior mean of the noise image,
+    E[u | x] = r^u R Sigma^{-1} x (cov(u, x) = r^u R), so h_hat + E[u | x] = x.  A conjugated
+    or dropped a, or a transposed product, fails one of the two."""
+    p = make_problem(4, 2, 6, config=213)
+    rng = np.random.default_rng(11)
+    rh = rng.gamma(1.0, 1.0, (p.I, p.J))
+    ru = rng.gamma(2.0, 0.5, (p.I, p.J))
+    lam = np.array([0.4, 1.7])
+    img = extract.spatial_image(p.x, p.a, p.Rp, p.b, rh, ru, lam)
+    assert img.shape == (p.I, p.J, p.M)
+    for i in range(p.I):
+        R = p.Rp[i] + lam[i] * np.outer(p.b[i], p.b[i].conj())
+        for j in range(p.J):
+            x = p.x[i, j].astype(np.complex128)
+            _, _, m = bruteforce.estep_joint(x, p.a[i], R, rh[i, j], ru[i, j])
+            assert np.max(np.abs(img[i, j] - m * p.a[i])) < 1e-12 * np.linalg.norm(x)
+            S = rh[i, j] * np.outer(p.a[i], p.a[i].conj()) + ru[i, j] * R
+            u_mean = ru[i, j] * R @ np.linalg.solve(S, x)
+            assert np.max(np.abs(img[i, j] + u_mean - x)) < 1e-12 * np.linalg.norm(x)
+
+
 # --- invariances ------------------------------------------------------------------------------
 
 def test_b_phase_invariance():
