@@ -254,6 +254,28 @@ rcscm_status rcscm_backward(rcscm_ctx* ctx, const void* x, const void* grad_s_ha
 rcscm_status rcscm_backproject(rcscm_ctx* ctx, const void* x, const void* W, const int* target,
                                void* a, void* Rp, void* b, float* ru0, float* lam0);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rcscm_run
+ * for one utterance with no context and no device allocation.  Arguments as
+ * rcscm_create + rcscm_run (x, a, Rp, b, rh0, ru0, lam0, K, rh, ru, lam,
+ * s_hat; params may be NULL; stream is a hipStream_t or NULL); the same
+ * kernel, so the outputs are bitwise those of rcscm_run on a context with
+ * the same params.  Nothing is kept: there is no state to continue from.
+ * Limits (ESHAPE / EINVAL otherwise): the ACCEL rule, RCSCM_LAMSUM_F64, no
+ * RCSCM_FLAG_CHECKPOINT, 1 <= J <= 8192, 1 <= I <= RCSCM_NOALLOC_MAX_ROWS.
+ * Scratch: one status word per row in a static device array of the library
+ * (RCSCM_NOALLOC_MAX_ROWS + 8 words, 256 KiB, per GPU, held until the process
+ * ends); calls that overlap on one GPU race on it.  check == 0: the call only
+ * enqueues work on the stream (capturable); data errors are not reported.
+ * check != 0: the call also reduces the status words, waits for the stream
+ * and returns the first data error as rcscm_sync would (ENONFINITE,
+ * ENOTNULL, ENOTPSD), described by rcscm_last_error(NULL). */
+#define RCSCM_NOALLOC_MAX_ROWS 65536
+rcscm_status rcscm_run_noalloc(int I, int J, int M, const rcscm_params* params, void* stream,
+                               const void* x, const void* a, const void* Rp, const void* b,
+                               const float* rh0, const float* ru0, const float* lam0, int K,
+                               float* rh, float* ru, float* lam, void* s_hat, int check);
+
 /* Frees every device buffer of the context (after waiting for its stream). */
 void rcscm_destroy(rcscm_ctx* ctx);
 

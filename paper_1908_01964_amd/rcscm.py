@@ -66,6 +66,8 @@ _SIGS = {
     "rcscm_run": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _I, _P, _P, _P, _P]),
     "rcscm_set_run_classes": (_I, [_P, _I, ctypes.POINTER(_I)]),
     "rcscm_get_run_classes": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "rcscm_run_noalloc": (_I, [_I, _I, _I, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, _P,
+                               _P, _I, _P, _P, _P, _P, _I]),
 }
 
 _lib = None
@@ -348,6 +350,22 @@ class Context:
                            (lam0, self.nrows, "lam0")):
             if t is not None and (t.dtype != torch.float32 or t.numel() != n):
                 raise ValueError(f"{name} must be float32 with {n} elements")
+
+
+def run_noalloc(I: int, J: int, M: int, x, a, Rp, b, K: int, out: dict, rh0=None, ru0=None,
+                lam0=None, stream=None, check=True, **params):
+    """rcscm_run_noalloc: one utterance, no context, no device allocation by the library.
+
+    out holds caller-allocated device tensors rh, ru (float32 [I*J]), lam (float32 [I]) and
+    s_hat (complex64 [I*J]); any may be missing.  check=False only enqueues (capturable)."""
+    p = _params(**params)
+    st = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().rcscm_run_noalloc(int(I), int(J), int(M), ctypes.byref(p),
+                                   ctypes.c_void_p(st.cuda_stream), _ptr(x), _ptr(a), _ptr(Rp),
+                                   _ptr(b), _ptr(rh0), _ptr(ru0), _ptr(lam0), int(K),
+                                   _ptr(out.get("rh")), _ptr(out.get("ru")), _ptr(out.get("lam")),
+                                   _ptr(out.get("s_hat")), 1 if check else 0), None)
+    return out
 
 
 def to_device(problem_or_list, device="cuda"):

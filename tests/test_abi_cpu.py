@@ -90,6 +90,27 @@ def test_null_context_calls():
     L.rcscm_destroy(None)
 
 
+@pytest.mark.parametrize("shape,kw,status,msg", [
+    ((4, 100, 4), dict(rule="naive"), R.EINVAL, "ACCEL"),
+    ((4, 100, 4), dict(lamsum="kahan32"), R.EINVAL, "LAMSUM_F64"),
+    ((4, 100, 4), dict(checkpoint=True), R.EINVAL, "checkpoints"),
+    ((4, 9000, 4), {}, R.ESHAPE, "8192"),
+    ((65537, 10, 2), {}, R.ESHAPE, "RCSCM_NOALLOC_MAX_ROWS"),
+    ((4, 100, 9), {}, R.ESHAPE, "M must"),
+])
+def test_noalloc_rejects_arguments_on_host(shape, kw, status, msg):
+    """rcscm_run_noalloc checks its limits before it touches a device."""
+    I, J, M = shape
+    p = R._params(**kw)
+    one = ctypes.c_void_p(1)  # never dereferenced: the call returns before any device work
+    st = pkg.lib().rcscm_run_noalloc(I, J, M, ctypes.byref(p), None, one, one, one, one, None,
+                                     None, None, 3, None, None, None, None, 1)
+    assert st == status and msg in pkg.lib().rcscm_last_error(None).decode()
+    st = pkg.lib().rcscm_run_noalloc(4, 100, 4, None, None, None, one, one, one, None, None, None,
+                                     3, None, None, None, None, 1)
+    assert st == R.EINVAL and "NULL" in pkg.lib().rcscm_last_error(None).decode()
+
+
 def test_workspace_bytes():
     w1 = pkg.workspace_bytes(513, [1000], [4])
     # per bin at least tau/sigma (16) + nu (4) + r^h, r^u (8)
