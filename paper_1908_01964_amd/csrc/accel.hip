@@ -48,7 +48,7 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
   for (int q = 0; q < BPL; ++q) {
     const int j = t + q * NT;
     if (j < J) {
-      ts[q] = tsig[base + j];
+      ts[q] = turn_sigma_bx(tsig[base + j], rc);
       vnu[q] = nu[base + j];
       vrh[q] = rh[base + j];
       vru[q] = ru[base + j];
@@ -299,14 +299,9 @@ __global__ __launch_bounds__(256) void extract_kernel(
     const float vrh = rh_in[bin], vru = ru_in[bin];
     if (rh_out != nullptr) rh_out[bin] = vrh;
     if (ru_out != nullptr) ru_out[bin] = vru;
-    if (s_hat != nullptr) {
-      const float4 ts = tsig[bin];
-      // s_hat = gamma rho^ax, rho^ax = tau^ax + sigma^ab sigma^bx / lambda
-      const float rx_re = fmaf(L.sp_re, ts.z, fmaf(-L.sp_im, ts.w, ts.x));
-      const float rx_im = fmaf(L.sp_re, ts.w, fmaf(L.sp_im, ts.z, ts.y));
-      const float g = vrh / fmaf(vrh, L.rho_aa, vru);
-      s_hat[bin] = make_float2(g * rx_re, g * rx_im);
-    }
+    // s_hat = gamma rho^ax, rho^ax = tau^ax + sigma^ab sigma^bx / lambda, in the turned form
+    // the fused launch uses (the same rounding)
+    if (s_hat != nullptr) s_hat[bin] = s_hat_of(turn_sigma_bx(tsig[bin], rc), vrh, vru, L);
   }
 }
 

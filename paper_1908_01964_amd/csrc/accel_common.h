@@ -39,6 +39,7 @@ struct LamTerms {
   float rho_aa;  // tau^aa + |sigma^ab|^2 / lambda
   float sp_re;   // sigma^ab / lambda
   float sp_im;
+  float sa_il;   // |sigma^ab| / lambda
   float rho_aaM;  // rho^aa / M
   float ilM;      // 1 / (M lambda)
   float itaaM;    // 1 / (M tau^aa), 0 when tau^aa == 0
@@ -50,6 +51,7 @@ __device__ __forceinline__ LamTerms lam_terms(const RowConstF& rc, float lam) {
   L.rho_aa = fmaf(rc.sab2, L.il, rc.t_aa);
   L.sp_re = rc.sab_re * L.il;
   L.sp_im = rc.sab_im * L.il;
+  L.sa_il = rc.sab_abs * L.il;
   L.rho_aaM = L.rho_aa * rc.invM;
   L.ilM = L.il * rc.invM;
   L.itaaM = rc.inv_t_aa * rc.invM;
@@ -81,7 +83,45 @@ __device__ __forceinline__ PhaseA phase_a(const float4 ts, float rh, float ru, c
   return o;
 }
 
+// The per-bin pair (tau^ax, sigma^bx) with sigma^bx turned by the phase of
+// sigma^ab: u = sigma^bx sigma^ab / |sigma^ab| (sigma^bx when sigma^ab = 0).
+// With it, sigma^ab sigma^bx = |sigma^ab| u and, for any w,
+// (sigma^bx - conj(sigma^ab) w) sigma^ab / |sigma^ab| = u - |sigma^ab| w, so
+// rho~ax, s_hat and |e| each take one real factor instead of a complex one.
+__device__ __forceinline__ float4 turn_sigma_bx(const float4 ts, const RowConstF& rc) {
+  float pr = 1.0f, pi = 0.0f;
+  if (rc.sab_abs > 0.0f) {
+    const float ia = 1.0f / rc.sab_abs;
+    pr = rc.sab_re * ia;
+    pi = rc.sab_im * ia;
+  }
+  return make_float4(ts.x, ts.y, fmaf(ts.z, pr, -ts.w * pi), fmaf(ts.z, pi, ts.w * pr));
+}
+
+// Phase A on the turned pair ts = (tau^ax, u) (turn_sigma_bx): the same
+// quantities as phase_a with
+//   rho~ax = tau^ax + (|sigma^ab| / lambda~) u,
+//   |e| = |u - |sigma^ab| w|.
+__device__ __forceinline__ PhaseA phase_a_turned(const float4 ts, float rh, float ru,
+                                                 const RowConstF& rc, const LamTerms& Lt,
+                                                 float inv_a2, float beta_a2) {
+  PhaseA o;
+  const float rx_re = fmaf(Lt.sa_il, ts.z, ts.x);
+  const float rx_im = fmaf(Lt.sa_il, ts.w, ts.y);
+  const float g = rh * frcp(fmaf(rh, Lt.rho_aa, ru));
+  o.w_re = g * rx_re;
+  o.w_im = g * rx_im;
+  o.cg = g * ru;
+  o.rh_new = fmaf(fmaf(o.w_re, o.w_re, fmaf(o.w_im, o.w_im, o.cg)), inv_a2, beta_a2);
+  const float e_re = fmaf(-rc.sab_abs, o.w_re, ts.z);
+  const float e_im = fmaf(-rc.sab_abs, o.w_im, ts.w);
+  o.E = fmaf(e_re, e_re, e_im * e_im);
+  o.t = fmaf(g, rc.sab2, o.E * frcp(ru));
+  return o;
+}
+
 // Phase B of one bin: new r^u given the new lambda (terms Ln); nuM = nu / M.
+// Reads only tau^ax from ts, so it serves both forms of the pair.
 __device__ __forceinline__ float phase_b(const float4 ts, float nuM, const PhaseA& A,
                                          const RowConstF& rc, const LamTerms& Ln) {
   const float d_re = fmaf(-A.w_re, rc.t_aa, ts.x);
@@ -166,6 +206,12 @@ __device__ __forceinline__ double dpp_f64(double v) {
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
   return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+// The DPP-moved value as the operand of an addition: out-of-row lanes would
+// read 0 (the identity), which lets the compiler fold the move into the add.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32_add_src(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

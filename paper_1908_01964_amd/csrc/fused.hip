@@ -73,6 +73,7 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
         A.tsig[base + j] = ts[q];
         A.nu[base + j] = vnu[q];
       }
+      ts[q] = turn_sigma_bx(ts[q], rc);
       vrh[q] = A.rh0 ? A.rh0[base + j] : A.rh_c;
       vru[q] = A.ru0 ? A.ru0[base + j] : A.ru_c;
       bad_state = bad_state || !(vrh[q] > 0.0f) || !(vru[q] > 0.0f) || !isfinite(vrh[q]) ||

@@ -173,7 +173,7 @@ __device__ __forceinline__ RowConstF row_const_f(const SetupLDS<M>& L, const Row
   F.inv_t_aa = (float)L.inv_taa;
   F.invM = (float)(1.0 / (double)M);
   F.invJ = 1.0f / (float)ri.J;
-  F.pad = 0.0f;
+  F.sab_abs = (float)sqrt(L.sab_re * L.sab_re + L.sab_im * L.sab_im);
   return F;
 }
 

@@ -34,7 +34,7 @@ struct RowConstF {
   float inv_t_aa;  // 1 / tau^(aa), or 0 when tau^(aa) == 0
   float invM;      // 1 / M
   float invJ;      // 1 / J
-  float pad;
+  float sab_abs;   // |sigma^(ab)|
 };
 
 // FP64 per-row setup results (precompute, objective, adjoint).

@@ -3,17 +3,20 @@
 // single-launch kernel.  Per iteration: phase A over the lane's bins, the
 // lambda frame sum (DPP within each wave, one LDS slot per wave, one barrier;
 // the slots are double-buffered so no second barrier is needed), phase B.
-// Under the F64 policy a lane adds its <= BPL terms in float and the lanes
-// and waves are combined in double.
+// Under the F64 policy a lane adds its <= BPL terms in float, the 64 lanes of
+// a wave are added in float by a fixed six-level tree, and the waves are
+// combined in double: for these non-negative terms the relative error is at
+// most (BPL + 5) u, u = 2^-24.
 #pragma once
 
 #include "accel_common.h"
 
 namespace rcscm {
 
-// Runs K iterations in place on (vrh, vru); returns the final lambda.  Bins
-// with frame index t + q*NT >= J do not enter the frame sum.  When ck_rh is
-// not null, theta at the start of every iteration is stored (checkpoints).
+// Runs K iterations in place on (vrh, vru); returns the final lambda.  ts
+// holds each bin's turned pair (tau^ax, u) of turn_sigma_bx.  Bins with frame
+// index t + q*NT >= J do not enter the frame sum.  When ck_rh is not null,
+// theta at the start of every iteration is stored (checkpoints).
 template <int NT, int BPL, int LS>
 __device__ __forceinline__ float resident_iterations(
     const float4 (&ts)[BPL], const float (&vnu)[BPL], float (&vrh)[BPL], float (&vru)[BPL],
@@ -45,7 +48,7 @@ __device__ __forceinline__ float resident_iterations(
     float tsum = 0.0f;  // F64 policy: the lane's <= BPL terms in float, lanes in double
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
-      A[q] = phase_a(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
+      A[q] = phase_a_turned(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
       const bool in = t + q * NT < J;
       if constexpr (LS == 0)
         tsum += in ? A[q].t : 0.0f;
@@ -53,8 +56,19 @@ __device__ __forceinline__ float resident_iterations(
         acc.add(A[q].t);
       vrh[q] = A[q].rh_new;
     }
-    if constexpr (LS == 0) acc.s = (double)tsum;
-    acc = wave_allreduce<LS>(acc);
+    if constexpr (LS == 0) {
+      // the wave's 64 lane sums in float by a fixed tree (DPP row rotations,
+      // then the four row sums), so every lane holds the same value
+      float v = tsum;
+      v += dpp_f32_add_src<kRowRor8>(v);
+      v += dpp_f32_add_src<kRowRor4>(v);
+      v += dpp_f32_add_src<kRowRor2>(v);
+      v += dpp_f32_add_src<kRowRor1>(v);
+      acc.s = (double)((readlane_f32(v, 0) + readlane_f32(v, 16)) +
+                       (readlane_f32(v, 32) + readlane_f32(v, 48)));
+    } else {
+      acc = wave_allreduce<LS>(acc);
+    }
     if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
     __syncthreads();
     const float lam_n = slots_sum<LS, NW>(red[k & 1]).mean(invJ);
@@ -68,10 +82,11 @@ __device__ __forceinline__ float resident_iterations(
 }
 
 // Wiener-filter estimate s_hat = gamma rho^ax of one bin at (r^h, r^u) and
-// the lambda terms L (posterior mean of s, inside eq. (15)).
+// the lambda terms L (posterior mean of s, inside eq. (15)), from the turned
+// pair ts = (tau^ax, u): rho^ax = tau^ax + (|sigma^ab| / lambda) u.
 __device__ __forceinline__ float2 s_hat_of(const float4 ts, float rh, float ru, const LamTerms& L) {
-  const float rx_re = fmaf(L.sp_re, ts.z, fmaf(-L.sp_im, ts.w, ts.x));
-  const float rx_im = fmaf(L.sp_re, ts.w, fmaf(L.sp_im, ts.z, ts.y));
+  const float rx_re = fmaf(L.sa_il, ts.z, ts.x);
+  const float rx_im = fmaf(L.sa_il, ts.w, ts.y);
   const float g = rh / fmaf(rh, L.rho_aa, ru);
   return make_float2(g * rx_re, g * rx_im);
 }
