@@ -152,6 +152,11 @@ struct LamAcc<0> {
     return r;
   }
   __device__ __forceinline__ float mean(double invJ) const { return (float)(s * invJ); }
+  __device__ __forceinline__ static LamAcc from(float v) {
+    LamAcc r;
+    r.s = (double)v;
+    return r;
+  }
 };
 
 template <>
@@ -207,12 +212,14 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
   return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
 }
-// The DPP-moved value as the operand of an addition: out-of-row lanes would
-// read 0 (the identity), which lets the compiler fold the move into the add.
+// The DPP-moved value as the operand of an addition (the row rotations have a
+// source in every lane; the identity 0 as the old value lets the compiler fold
+// the move into the add).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32_add_src(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
 }
+
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -223,6 +230,24 @@ __device__ __forceinline__ float readlane_f32(float v, int lane) {
 }
 
 constexpr int kRowRor8 = 0x128, kRowRor4 = 0x124, kRowRor2 = 0x122, kRowRor1 = 0x121;
+
+// Sum of a float over the 64 lanes of a wave by a fixed tree, the same value
+// in every lane: DPP row rotations by 8, 4, 2, 1 leave each 16-lane row's sum
+// in all its lanes; swapping the 32-lane halves adds rows 0 + 2 and 1 + 3,
+// swapping neighbouring rows adds those two.  For non-negative terms the
+// relative error is at most 6 u.
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  v += dpp_f32_add_src<kRowRor8>(v);
+  v += dpp_f32_add_src<kRowRor4>(v);
+  v += dpp_f32_add_src<kRowRor2>(v);
+  v += dpp_f32_add_src<kRowRor1>(v);
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false,
+                                                  false);
+  v = __int_as_float(h[0]) + __int_as_float(h[1]);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false,
+                                                  false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
 
 template <int LS, int CTRL>
 __device__ __forceinline__ LamAcc<LS> rot(const LamAcc<LS>& a);

@@ -30,7 +30,8 @@ struct SetupLDS {
   double2 sR[M][M];       // projected, Hermitised R'
   double2 sQ[M][M];       // (R')^+
   double2 aug[M][2 * M];  // Gauss-Jordan work array
-  double2 sa[M], sb[M], sy[M], sc[M];
+  double2 sa[M], sb[M], sc[M];
+  double2 sbr[M], syr[M];  // b as given and R' b with it
   double taa, inv_taa, sab_re, sab_im, det_a, shift;
   unsigned flags;
 };
@@ -62,80 +63,98 @@ __device__ __forceinline__ SetupIn row_setup_load(const double2* __restrict__ Rp
   return in;
 }
 
+// 1/sqrt(v) for v > 0: the hardware estimate refined by two Newton-Raphson
+// steps y <- y (3 - v y^2) / 2, each of which doubles the number of correct bits.
+__device__ __forceinline__ double rsqrt_f64_nr(double v) {
+  double y = __builtin_amdgcn_rsq(v);
+  y = y * fma(-0.5 * v, y * y, 1.5);
+  return y * fma(-0.5 * v, y * y, 1.5);
+}
+
 // Row setup by wave 0 (lanes t < 64) from its loaded inputs.  Lane t < M*M
-// owns entry (i, j) = (t / M, t % M); sums over lanes are uniform DPP
-// reductions, several at a time.  With y = R' b and e_b = b^H R' b (real part),
-// the projected, Hermitised matrix is
+// owns entry (i, j) = (t / M, t % M).  Everything before the elimination
+// comes from ONE batch of wave sums, on b as given (b0, ||b0|| = nb) and
+// y0 = R' b0: ||b0||^2, a^H b0, tr R', b0^H R' b0, ||R' b0||^2, ||R'||_F^2.
+// With b = b0 / nb, y = R' b = y0 / nb and e_b = b^H R' b,
 //   P R' P (Hermitised) = (R' + R'^H)/2 - b y^H - y b^H + e_b b b^H,  P = I - b b^H,
-// computed entrywise without a transpose through LDS.
+// and its trace is tr R' - e_b, so no further sum is needed; the second and
+// last sum, tau^aa = a^H (R')^+ a, runs over the lanes' entries of (R')^+
+// beside the products c = (R')^+ a.
 template <int M>
 __device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
   const int t = threadIdx.x;
   const int i = t / M, j = t % M;
   const bool ent = t < M * M;
-  const double2 r = in.r, av = in.av;
-  double2 bv = in.bv;
-  const bool fin = zfinite(r) && zfinite(in.rt) && zfinite(av) && zfinite(bv);
-  const double2 ab0 = zmulc(av, bv);  // a^H b before normalising b
-  double s1[5] = {fin ? 0.0 : 1.0, r.x * r.x + r.y * r.y, bv.x * bv.x + bv.y * bv.y, ab0.x, ab0.y};
-  wave_sums<5, M * M>(s1);
-  const double nbad = s1[0], nr2 = s1[1], nb2 = s1[2];
-  unsigned f = 0u;
-  const double nb = sqrt(nb2);
-  if (nbad > 0.0) f |= ST_NONFINITE_IN;
-  if (!(nb > 0.0) || nbad > 0.0)
-    f |= ST_NOT_NULL;
-  else if (fabs(nb - 1.0) > 1e-6)
-    f |= ST_B_NOT_UNIT;
-  const double inb = (nb > 0.0 && nbad == 0.0) ? 1.0 / nb : 0.0;
-  bv = make_double2(bv.x * inb, bv.y * inb);
-  if (ent) L.aug[i][j] = r;  // R' for the product y = R' b
+  const double2 r = in.r, av = in.av, b0 = in.bv;
+  const bool fin = zfinite(r) && zfinite(in.rt) && zfinite(av) && zfinite(b0);
+  if (ent) L.aug[i][j] = r;  // R' for the products y0 = R' b0
   if (t < M) {
     L.sa[t] = av;
-    L.sb[t] = bv;
+    L.sbr[t] = b0;
   }
   wave_sync();
-  double2 y = make_double2(0.0, 0.0);  // y = R' b
+  double2 y0 = make_double2(0.0, 0.0);  // row t of R' b0
   if (t < M) {
 #pragma unroll
     for (int n = 0; n < M; ++n) {
-      const double2 p = zmul(L.aug[t][n], L.sb[n]);
-      y.x += p.x;
-      y.y += p.y;
+      const double2 p = zmul(L.aug[t][n], L.sbr[n]);
+      y0.x += p.x;
+      y0.y += p.y;
     }
-    L.sy[t] = y;
+    L.syr[t] = y0;
   }
-  double s2[2] = {y.x * y.x + y.y * y.y, zmulc(bv, y).x};  // ||R' b||^2, b^H R' b
-  wave_sums<2, M>(s2);
-  const double ny2 = s2[0], be = s2[1];
-  if (!(ny2 <= 1e-12 * nr2)) f |= ST_NOT_NULL;  // ||R' b|| <= 1e-6 ||R'||_F
-  wave_sync();
-  double2 rhm = make_double2(0.0, 0.0), bb = rhm;
-  if (ent) {
-    const double2 bi = L.sb[i], bj = L.sb[j], yi = L.sy[i], yj = L.sy[j];
-    const double2 byj = zmul(bi, zconj(yj));
-    const double2 ybj = zmul(yi, zconj(bj));
-    bb = zmul(bi, zconj(bj));
-    rhm = make_double2(0.5 * (r.x + in.rt.x) - byj.x - ybj.x + be * bb.x,
-                       0.5 * (r.y - in.rt.y) - byj.y - ybj.y + be * bb.y);
-  }
-  double s3[1] = {(ent && i == j) ? rhm.x : 0.0};
-  wave_sums<1, M * M>(s3);
-  const double tr = s3[0];
+  const double2 ab0 = zmulc(av, b0);  // a^H b0, lanes t < M
+  double s1[8] = {fin ? 0.0 : 1.0,
+                  r.x * r.x + r.y * r.y,
+                  b0.x * b0.x + b0.y * b0.y,
+                  ab0.x,
+                  ab0.y,
+                  (ent && i == j) ? r.x : 0.0,
+                  zmulc(b0, y0).x,
+                  y0.x * y0.x + y0.y * y0.y};
+  wave_sums<8, M * M>(s1);
+  const double nbad = s1[0], nr2 = s1[1], nb2 = s1[2];
+  unsigned f = 0u;
+  if (nbad > 0.0) f |= ST_NONFINITE_IN;
+  const bool bok = nb2 > 0.0 && nbad == 0.0;
+  const double inb = bok ? rsqrt_f64_nr(nb2) : 0.0;  // 1 / ||b0||
+  if (!bok)
+    f |= ST_NOT_NULL;
+  else if (fabs(nb2 * inb - 1.0) > 1e-6)
+    f |= ST_B_NOT_UNIT;
+  const double inb2 = inb * inb;
+  const double be = s1[6] * inb2;                     // b^H R' b
+  if (!(s1[7] * inb2 <= 1e-12 * nr2)) f |= ST_NOT_NULL;  // ||R' b|| <= 1e-6 ||R'||_F
+  const double tr = s1[5] - be;                       // tr P R' P
   const double sh = tr > 0.0 ? tr / (double)(M - 1) : 1.0;
+  wave_sync();
+  double2 rhm = make_double2(0.0, 0.0), bb = rhm, ai = rhm, aj = rhm;
   if (ent) {
+    const double2 bi0 = L.sbr[i], bj0 = L.sbr[j], yi0 = L.syr[i], yj0 = L.syr[j];
+    ai = L.sa[i];
+    aj = L.sa[j];
+    // b_i conj(y_j), y_i conj(b_j) and b_i conj(b_j), each scaled by 1/||b0||^2
+    const double2 byj = zmul(bi0, zconj(yj0));
+    const double2 ybj = zmul(yi0, zconj(bj0));
+    const double2 bb0 = zmul(bi0, zconj(bj0));
+    bb = make_double2(bb0.x * inb2, bb0.y * inb2);
+    rhm = make_double2(0.5 * (r.x + in.rt.x) - (byj.x + ybj.x) * inb2 + be * bb.x,
+                       0.5 * (r.y - in.rt.y) - (byj.y + ybj.y) * inb2 + be * bb.y);
     L.sR[i][j] = rhm;
     L.aug[i][j] = make_double2(rhm.x + sh * bb.x, rhm.y + sh * bb.y);
     L.aug[i][M + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
+  if (t < M) L.sb[t] = make_double2(b0.x * inb, b0.y * inb);
   wave_sync();
   double pivprod = 1.0;
   // A = R' + s b b^H has trace tr + s; a pivot below 1e-13 of it means rank(R') < M-1
   const bool pd = gj_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + sh), &pivprod);
+  double2 q = make_double2(0.0, 0.0);
   if (ent) {  // (R')^+ = A^{-1} - b b^H / s, Hermitised
     const double ish = 1.0 / sh;
     const double2 u = L.aug[i][M + j], v = L.aug[j][M + i];
-    L.sQ[i][j] = make_double2(0.5 * (u.x + v.x) - bb.x * ish, 0.5 * (u.y - v.y) - bb.y * ish);
+    q = make_double2(0.5 * (u.x + v.x) - bb.x * ish, 0.5 * (u.y - v.y) - bb.y * ish);
+    L.sQ[i][j] = q;
   }
   wave_sync();
   double2 cc = make_double2(0.0, 0.0);  // c = (R')^+ a
@@ -148,11 +167,11 @@ __device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
     }
     L.sc[t] = cc;
   }
-  double s4[1] = {zmulc(av, cc).x};
-  wave_sums<1, M>(s4);
+  double s2[1] = {zmulc(ai, zmul(q, aj)).x};  // conj(a_i) Q_ij a_j
+  wave_sums<1, M * M>(s2);
   if (!pd) f |= ST_NOT_PSD;
   if (t == 0) {
-    const double taa = fmax(s4[0], 0.0);
+    const double taa = fmax(s2[0], 0.0);
     L.taa = taa;
     L.inv_taa = taa > 0.0 ? rcp_f64_nr(taa) : 0.0;
     L.sab_re = s1[3] * inb;

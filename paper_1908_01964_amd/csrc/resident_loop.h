@@ -6,19 +6,16 @@
 // Under the F64 policy a lane adds its <= BPL terms in float, the 64 lanes of
 // a wave are added in float by a fixed six-level tree, and the waves are
 // combined in double: for these non-negative terms the relative error is at
-// most (BPL + 5) u, u = 2^-24.
+// most (BPL + 5) u, u = 2^-24.  The result is the same in every lane and run.
 #pragma once
 
 #include "accel_common.h"
 
 namespace rcscm {
 
-// Runs K iterations in place on (vrh, vru); returns the final lambda.  ts
-// holds each bin's turned pair (tau^ax, u) of turn_sigma_bx.  Bins with frame
-// index t + q*NT >= J do not enter the frame sum.  When ck_rh is not null,
-// theta at the start of every iteration is stored (checkpoints).
-template <int NT, int BPL, int LS>
-__device__ __forceinline__ float resident_iterations(
+// The loop of resident_iterations, with or without the checkpoint stores (CK).
+template <int NT, int BPL, int LS, bool CK>
+__device__ __forceinline__ float resident_loop(
     const float4 (&ts)[BPL], const float (&vnu)[BPL], float (&vrh)[BPL], float (&vru)[BPL],
     const RowConstF& rc, float lam_t, int row, int J, long long base, int K, float inv_a2,
     float beta_a2, uint64_t (*red)[NT / 64], float* __restrict__ ck_rh,
@@ -32,7 +29,7 @@ __device__ __forceinline__ float resident_iterations(
   for (int q = 0; q < BPL; ++q) nuM[q] = vnu[q] * rc.invM;
   LamTerms Lt = lam_terms(rc, lam_t);
   for (int k = 0; k < K; ++k) {
-    if (ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
+    if constexpr (CK) {  // checkpoint theta at the start of iteration k
 #pragma unroll
       for (int q = 0; q < BPL; ++q) {
         const int j = t + q * NT;
@@ -45,31 +42,26 @@ __device__ __forceinline__ float resident_iterations(
     }
     LamAcc<LS> acc;
     PhaseA A[BPL];
-    float tsum = 0.0f;  // F64 policy: the lane's <= BPL terms in float, lanes in double
+    float tsum;  // F64 policy: the lane's <= BPL terms in float
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       A[q] = phase_a_turned(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
       const bool in = t + q * NT < J;
-      if constexpr (LS == 0)
-        tsum += in ? A[q].t : 0.0f;
-      else if (in)
+      if constexpr (LS == 0) {
+        const float tq = in ? A[q].t : 0.0f;
+        tsum = q == 0 ? tq : tsum + tq;
+      } else if (in) {
         acc.add(A[q].t);
+      }
       vrh[q] = A[q].rh_new;
     }
     if constexpr (LS == 0) {
-      // the wave's 64 lane sums in float by a fixed tree (DPP row rotations,
-      // then the four row sums), so every lane holds the same value
-      float v = tsum;
-      v += dpp_f32_add_src<kRowRor8>(v);
-      v += dpp_f32_add_src<kRowRor4>(v);
-      v += dpp_f32_add_src<kRowRor2>(v);
-      v += dpp_f32_add_src<kRowRor1>(v);
-      acc.s = (double)((readlane_f32(v, 0) + readlane_f32(v, 16)) +
-                       (readlane_f32(v, 32) + readlane_f32(v, 48)));
+      const float v = wave_sum_f32(tsum);
+      if ((t & 63) == 0) red[k & 1][wave] = LamAcc<0>::from(v).pack();
     } else {
       acc = wave_allreduce<LS>(acc);
+      if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
     }
-    if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
     __syncthreads();
     const float lam_n = slots_sum<LS, NW>(red[k & 1]).mean(invJ);
     const LamTerms Ln = lam_terms(rc, lam_n);
@@ -79,6 +71,26 @@ __device__ __forceinline__ float resident_iterations(
     Lt = Ln;
   }
   return lam_t;
+}
+
+// Runs K iterations in place on (vrh, vru); returns the final lambda.  ts
+// holds each bin's turned pair (tau^ax, u) of turn_sigma_bx.  Bins with frame
+// index t + q*NT >= J do not enter the frame sum.  When ck_rh is not null,
+// theta at the start of every iteration is stored (checkpoints); the test is
+// made once, outside the loop (a test per iteration cost 1.7 % of the fused
+// launch at M = 4, I = 513, J = 1000, K = 20).
+template <int NT, int BPL, int LS>
+__device__ __forceinline__ float resident_iterations(
+    const float4 (&ts)[BPL], const float (&vnu)[BPL], float (&vrh)[BPL], float (&vru)[BPL],
+    const RowConstF& rc, float lam_t, int row, int J, long long base, int K, float inv_a2,
+    float beta_a2, uint64_t (*red)[NT / 64], float* __restrict__ ck_rh,
+    float* __restrict__ ck_ru, float* __restrict__ ck_lam, long long ck_sb, int ck_sr) {
+  if (ck_rh != nullptr)
+    return resident_loop<NT, BPL, LS, true>(ts, vnu, vrh, vru, rc, lam_t, row, J, base, K,
+                                            inv_a2, beta_a2, red, ck_rh, ck_ru, ck_lam, ck_sb,
+                                            ck_sr);
+  return resident_loop<NT, BPL, LS, false>(ts, vnu, vrh, vru, rc, lam_t, row, J, base, K, inv_a2,
+                                           beta_a2, red, nullptr, nullptr, nullptr, 0, 0);
 }
 
 // Wiener-filter estimate s_hat = gamma rho^ax of one bin at (r^h, r^u) and
