@@ -41,14 +41,15 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   __shared__ uint64_t red[2][NW];
   __shared__ unsigned cflag;
 
-  const bool al4 = (M & 1) == 0 && (ri.x_off & 1) == 0;
   // x of G bins per lane in registers ahead of the precomputation (G M complex registers)
   constexpr int GMAX = NT >= 1024 ? (M <= 4 ? 2 : 1) : (M <= 2 ? 8 : (M <= 4 ? 4 : 2));
   constexpr int G = BPL < GMAX ? BPL : GMAX;
   float2 xv[G][M];
+  // Lanes past the row's last frame load that frame again (their values are
+  // not used), so the loads need no branch.
   auto load_bin = [&](int q, float2(&v)[M]) {
     const int j = t + q * NT;
-    if (j < J) load_x<M>(A.x + ri.x_off + (long long)j * M, al4, v);
+    load_x8<M>(A.x + ri.x_off + (long long)(j < J ? j : J - 1) * M, v);
   };
   // The setup's loads first, then only the first bin of x per lane: every
   // workgroup of the launch starts at once, and the more x is in flight the

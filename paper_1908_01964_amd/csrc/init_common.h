@@ -37,13 +37,17 @@ struct SetupLDS {
 };
 
 // The setup's inputs as held by the lanes of wave 0: lane t < M*M holds
-// R'[t / M][t % M] and R'[t % M][t / M], lane t < M holds a[t] and b[t].
+// R'[t / M][t % M] and R'[t % M][t / M], lane t < M holds a[t] and b[t]
+// (the other lanes hold copies of entry 0, which the setup leaves out).
 struct SetupIn {
   double2 r, rt, av, bv;
 };
 
-// Issues the setup's loads (only lanes t < M*M of wave 0 load), so a kernel
-// can put them ahead of its own loads in the memory queue.
+// Issues the setup's loads, so a kernel can put them ahead of its own loads in
+// the memory queue.  Only wave 0 loads; every lane of it does, lanes beyond the
+// matrix (t >= M*M) and beyond the vectors (t >= M) loading entry 0 again, so
+// the loads are straight-line code and a later wait for them need not also
+// wait for loads issued after them.  row_setup_wave masks those duplicates.
 template <int M>
 __device__ __forceinline__ SetupIn row_setup_load(const double2* __restrict__ Rp,
                                                   const double2* __restrict__ a,
@@ -52,13 +56,13 @@ __device__ __forceinline__ SetupIn row_setup_load(const double2* __restrict__ Rp
   const int t = threadIdx.x;
   SetupIn in;
   in.r = in.rt = in.av = in.bv = make_double2(0.0, 0.0);
-  if (t < M * M) {
-    in.r = Rp[ri.rp_off + t];
-    in.rt = Rp[ri.rp_off + (t % M) * M + t / M];
-  }
-  if (t < M) {
-    in.av = a[ri.a_off + t];
-    in.bv = b[ri.a_off + t];
+  if (t < 64) {  // uniform per wave
+    const int e = t < M * M ? t : 0;
+    const int m = t < M ? t : 0;
+    in.r = Rp[ri.rp_off + e];
+    in.rt = Rp[ri.rp_off + (e % M) * M + e / M];
+    in.av = a[ri.a_off + m];
+    in.bv = b[ri.a_off + m];
   }
   return in;
 }
@@ -103,12 +107,13 @@ __device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
     }
     L.syr[t] = y0;
   }
+  const bool vec = t < M;
   const double2 ab0 = zmulc(av, b0);  // a^H b0, lanes t < M
   double s1[8] = {fin ? 0.0 : 1.0,
-                  r.x * r.x + r.y * r.y,
-                  b0.x * b0.x + b0.y * b0.y,
-                  ab0.x,
-                  ab0.y,
+                  ent ? r.x * r.x + r.y * r.y : 0.0,
+                  vec ? b0.x * b0.x + b0.y * b0.y : 0.0,
+                  vec ? ab0.x : 0.0,
+                  vec ? ab0.y : 0.0,
                   (ent && i == j) ? r.x : 0.0,
                   zmulc(b0, y0).x,
                   y0.x * y0.x + y0.y * y0.y};
@@ -252,6 +257,14 @@ __device__ void write_row_constants(const SetupLDS<M>& L, int row, const RowInfo
     if (!(l > 0.0f) || !isfinite(l)) f |= ST_NONFINITE_STATE;
     status[row] = f;
   }
+}
+
+// Loads the M complex64 observations of one bin as 8-byte values (no alignment
+// test, so no branch around the loads).
+template <int M>
+__device__ __forceinline__ void load_x8(const float2* __restrict__ xp, float2 (&xv)[M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) xv[m] = xp[m];
 }
 
 // Loads the M complex64 observations of one bin (16-byte pairs when aligned).
