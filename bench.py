@@ -268,6 +268,42 @@ def time_stream(I, Js, Ms, inputs, K, reps, torch):
             "timing": f"HIP events around {reps} x rcscm_iterate({K}) (graph), per pass"}
 
 
+def time_stream_hbm(torch, a1, Rp1, b1, I=1025, J=16000, M=4, K=20, reps=3):
+    """The STREAM schedule at a size whose per-bin state (28 B per bin, 459 MB) does not fit
+    the 256 MB Infinity Cache, so every pass streams it from HBM: I = 1025 rows of J = 16000
+    frames, M = 4.  The spatial model of each row is the sinc-coherence model of workload 1
+    (row i uses frequency i mod 513); x is seeded complex Gaussian noise (the kernel's speed
+    does not depend on the values).  a1, Rp1, b1: workload 1's per-row model on the device."""
+    from paper_1908_01964_amd import Context
+    rows = torch.arange(I) % 513
+    a = a1.reshape(513, M)[rows].reshape(-1).contiguous()
+    b = b1.reshape(513, M)[rows].reshape(-1).contiguous()
+    Rp = Rp1.reshape(513, M * M)[rows].reshape(-1).contiguous()
+    g = torch.Generator(device=a.device)
+    g.manual_seed(190801964)
+    x = torch.randn(I * J * M, dtype=torch.complex64, device=a.device, generator=g)
+    nbins = I * J
+    ctx = Context(I, [J], [M], schedule="stream", graph=True)
+    ctx.init(x, a, Rp, b)
+    ctx.iterate(K)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.iterate(K)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ctx.close()
+    pass_us = e0.elapsed_time(e1) * 1e3 / reps / K
+    gbs = STREAM_BYTES_PER_UPDATE * nbins / (pass_us * 1e-6) / 1e9
+    return {"kernel": "accel_stream_kernel", "shape": f"M={M} I={I} J={J} K={K}",
+            "us_per_pass": pass_us, "bytes_per_update": STREAM_BYTES_PER_UPDATE,
+            "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / PEAK_HBM_GBS,
+            "state_bytes": 28 * nbins, "state_residence": "HBM (state > 256 MiB)",
+            "timing": f"HIP events around {reps} x rcscm_iterate({K}) (graph), per pass"}
+
+
 def row_error_stats(gpu, ref):
     """Normwise relative error per quantity (the parity bar), the largest normwise error of a
     single frequency row (lambda: per row), and the elementwise max and 99.9th percentile of
@@ -523,8 +559,11 @@ def main():
     # The STREAM schedule and the same work as three calls (init, iterate, extract), for the
     # per-phase breakdown.
     stream = None
+    stream_hbm = None
     if args.workload in (1, 2, 4) and not args.no_stream:
         stream = time_stream(I, Js, Ms, inputs, K, 5 if args.workload == 1 else 2, torch)
+        if args.workload == 1:
+            stream_hbm = time_stream_hbm(torch, *inputs[1:])
     fused = args.schedule != "stream" and max(Js) <= 8192 and not args.modular
     msteps = args.steps if not fused else max(10, args.steps // 4)
     out_m = {k: torch.empty_like(v) for k, v in out.items()}
@@ -604,11 +643,16 @@ def main():
                 "launch_us": launch_us, "bytes_per_update": STREAM_BYTES_PER_UPDATE}
     hbm_target = None
     if stream is not None:
+        st_h = stream_hbm if stream_hbm is not None else stream
         hbm_target = {
             "target_frac": HBM_TARGET_FRAC,
-            "stream_frac": stream["frac_of_hbm_peak"],
+            "stream_frac_this_workload": stream["frac_of_hbm_peak"],
             "stream_state_residence": stream["state_residence"],
-            "met_by_stream": stream["frac_of_hbm_peak"] >= HBM_TARGET_FRAC,
+            "stream_frac_hbm_resident": (stream_hbm["frac_of_hbm_peak"]
+                                         if stream_hbm is not None else None),
+            # judged only where the stream's state lives in HBM
+            "met_by_stream": (st_h["frac_of_hbm_peak"] >= HBM_TARGET_FRAC
+                              if st_h["state_residence"].startswith("HBM") else None),
             "note": ("the target applies to the streaming form (36 B per bin-update). The fused "
                      "step reads x once and keeps the iteration on chip, so it is not HBM-bound; "
                      "its 36-B-per-update equivalent bandwidth is on-chip traffic and may exceed "
@@ -637,6 +681,8 @@ def main():
         line["run_with_state"] = with_state
     if stream is not None:
         line["stream"] = stream
+        if stream_hbm is not None:
+            line["stream_hbm"] = stream_hbm
         line["hbm_target"] = hbm_target
     if naive is not None:
         line["naive"] = naive

@@ -153,13 +153,24 @@ __device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
   wave_sync();
   double pivprod = 1.0;
   // A = R' + s b b^H has trace tr + s; a pivot below 1e-13 of it means rank(R') < M-1
-  const bool pd = gj_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + sh), &pivprod);
   double2 q = make_double2(0.0, 0.0);
-  if (ent) {  // (R')^+ = A^{-1} - b b^H / s, Hermitised
-    const double ish = 1.0 / sh;
-    const double2 u = L.aug[i][M + j], v = L.aug[j][M + i];
-    q = make_double2(0.5 * (u.x + v.x) - bb.x * ish, 0.5 * (u.y - v.y) - bb.y * ish);
-    L.sQ[i][j] = q;
+  bool pd;
+  if constexpr (M <= 4) {  // (R')^+ = A^{-1} - b b^H / s, A^{-1} exactly Hermitian
+    double2 ainv;
+    pd = ldl_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + sh), &pivprod, &ainv);
+    if (ent) {
+      const double ish = 1.0 / sh;
+      q = make_double2(ainv.x - bb.x * ish, ainv.y - bb.y * ish);
+      L.sQ[i][j] = q;
+    }
+  } else {  // (R')^+ = A^{-1} - b b^H / s, Hermitised
+    pd = gj_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + sh), &pivprod);
+    if (ent) {
+      const double ish = 1.0 / sh;
+      const double2 u = L.aug[i][M + j], v = L.aug[j][M + i];
+      q = make_double2(0.5 * (u.x + v.x) - bb.x * ish, 0.5 * (u.y - v.y) - bb.y * ish);
+      L.sQ[i][j] = q;
+    }
   }
   wave_sync();
   double2 cc = make_double2(0.0, 0.0);  // c = (R')^+ a

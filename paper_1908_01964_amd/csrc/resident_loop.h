@@ -13,7 +13,8 @@
 
 namespace rcscm {
 
-// The loop of resident_iterations, with or without the checkpoint stores (CK).
+// The loop of resident_iterations; with CK false it has no checkpoint stores,
+// with CK true it stores when ck_rh is not null.
 template <int NT, int BPL, int LS, bool CK>
 __device__ __forceinline__ float resident_loop(
     const float4 (&ts)[BPL], const float (&vnu)[BPL], float (&vrh)[BPL], float (&vru)[BPL],
@@ -29,7 +30,7 @@ __device__ __forceinline__ float resident_loop(
   for (int q = 0; q < BPL; ++q) nuM[q] = vnu[q] * rc.invM;
   LamTerms Lt = lam_terms(rc, lam_t);
   for (int k = 0; k < K; ++k) {
-    if constexpr (CK) {  // checkpoint theta at the start of iteration k
+    if (CK && ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
 #pragma unroll
       for (int q = 0; q < BPL; ++q) {
         const int j = t + q * NT;
@@ -76,16 +77,19 @@ __device__ __forceinline__ float resident_loop(
 // Runs K iterations in place on (vrh, vru); returns the final lambda.  ts
 // holds each bin's turned pair (tau^ax, u) of turn_sigma_bx.  Bins with frame
 // index t + q*NT >= J do not enter the frame sum.  When ck_rh is not null,
-// theta at the start of every iteration is stored (checkpoints); the test is
-// made once, outside the loop (a test per iteration cost 1.7 % of the fused
-// launch at M = 4, I = 513, J = 1000, K = 20).
+// theta at the start of every iteration is stored (checkpoints).  Up to four
+// bins per lane the test is made once, outside the loop (a test per iteration
+// cost 1.7 % of the fused launch at M = 4, I = 513, J = 1000, K = 20); with
+// eight, two copies of the loop raised the register count past the
+// occupancy steps (256 x 8: 108 -> 130 VGPRs, 1024 x 8: spills), so the test
+// stays inside.
 template <int NT, int BPL, int LS>
 __device__ __forceinline__ float resident_iterations(
     const float4 (&ts)[BPL], const float (&vnu)[BPL], float (&vrh)[BPL], float (&vru)[BPL],
     const RowConstF& rc, float lam_t, int row, int J, long long base, int K, float inv_a2,
     float beta_a2, uint64_t (*red)[NT / 64], float* __restrict__ ck_rh,
     float* __restrict__ ck_ru, float* __restrict__ ck_lam, long long ck_sb, int ck_sr) {
-  if (ck_rh != nullptr)
+  if (BPL > 4 || ck_rh != nullptr)
     return resident_loop<NT, BPL, LS, true>(ts, vnu, vrh, vru, rc, lam_t, row, J, base, K,
                                             inv_a2, beta_a2, red, ck_rh, ck_ru, ck_lam, ck_sb,
                                             ck_sr);

@@ -83,4 +83,97 @@ __device__ bool gj_inverse_hpd_wave(double2 (*aug)[2 * M], double tol, double* p
   return ok;
 }
 
+// Entry (i, j) of the inverse of a Hermitian positive-definite M x M matrix A
+// (M <= 4) for lane t < M*M of wave 0, (i, j) = (t / M, t % M).  a is LDS
+// [M][2M] with A in its left half on entry; the right half is overwritten.
+// Every lane of the wave factorises A = L D L^H (L unit lower triangular, D
+// real diagonal; no pivoting, stable for HPD matrices) in its own registers,
+// so the M dependent pivot steps need no LDS round trip.  Lane 0 then stores
+// X = L^{-1} (below the diagonal) and 1/D (on it) in the right half, and lane
+// (i, j) forms (A^{-1})_ij = sum_{m >= max(i, j)} conj(X_mi) X_mj / d_m
+// (X_mm = 1), which is exactly Hermitian in (i, j).  Returns false (and
+// continues with a clamped pivot) when a pivot is <= tol; *pivprod receives
+// the product of the pivots (= det A).
+template <int M>
+__device__ bool ldl_inverse_hpd_wave(double2 (*a)[2 * M], double tol, double* pivprod,
+                                     double2* inv_ij) {
+  static_assert(M <= 4, "registers hold the whole factorisation");
+  const int t = threadIdx.x;
+  const int i = t / M, j = t % M;
+  double2 A[M][M];
+#pragma unroll
+  for (int r = 0; r < M; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) A[r][c] = a[r][c];  // lower triangle (a broadcast read)
+  double2 Lm[M][M];
+  double d[M], id[M];
+  bool ok = true;
+  double prod = 1.0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double dk = A[k][k].x;
+#pragma unroll
+    for (int m = 0; m < k; ++m) dk -= (Lm[k][m].x * Lm[k][m].x + Lm[k][m].y * Lm[k][m].y) * d[m];
+    if (!(dk > tol)) {
+      ok = false;
+      dk = fmax(tol, 1e-300);
+    }
+    prod *= dk;
+    d[k] = dk;
+    id[k] = rcp_f64_nr(dk);
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) {
+      double2 v = A[r][k];
+#pragma unroll
+      for (int m = 0; m < k; ++m) {
+        const double2 p = zmul(Lm[r][m], zconj(Lm[k][m]));
+        v.x -= p.x * d[m];
+        v.y -= p.y * d[m];
+      }
+      Lm[r][k] = make_double2(v.x * id[k], v.y * id[k]);
+    }
+  }
+  // X = L^{-1}: X_rr = 1, X_rc = -(L_rc + sum_{c < m < r} L_rm X_mc) for r > c
+  double2 X[M][M];
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+#pragma unroll
+    for (int r = c + 1; r < M; ++r) {
+      double2 v = Lm[r][c];
+#pragma unroll
+      for (int m = c + 1; m < r; ++m) {
+        const double2 p = zmul(Lm[r][m], X[m][c]);
+        v.x += p.x;
+        v.y += p.y;
+      }
+      X[r][c] = make_double2(-v.x, -v.y);
+    }
+  if (t == 0) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      a[r][M + r] = make_double2(id[r], 0.0);
+#pragma unroll
+      for (int c = 0; c < r; ++c) a[r][M + c] = X[r][c];
+    }
+  }
+  wave_sync();
+  double2 acc = make_double2(0.0, 0.0);
+  if (t < M * M) {
+    const int lo = i > j ? i : j;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (m < lo) continue;
+      const double im = a[m][M + m].x;
+      const double2 xi = m == i ? make_double2(1.0, 0.0) : a[m][M + i];
+      const double2 xj = m == j ? make_double2(1.0, 0.0) : a[m][M + j];
+      const double2 p = zmulc(xi, xj);  // conj(X_mi) X_mj
+      acc.x += p.x * im;
+      acc.y += p.y * im;
+    }
+  }
+  *inv_ij = acc;
+  *pivprod = prod;
+  return ok;
+}
+
 }  // namespace rcscm
