@@ -541,7 +541,16 @@ def main():
         ctxn.sync()
         ctxn.close()
         naive = {"value": updates * args.naive_steps / wall_n,
-                 "ms_per_step": wall_n / args.naive_steps * 1e3, "phases_us": phases_n}
+                 "ms_per_step": wall_n / args.naive_steps * 1e3, "phases_us": phases_n,
+                 "u_hat": "stored packed between the two launches"}
+        # the other form of the comparator: U^ recomputed in the second launch
+        ctxn = Context(I, Js, Ms, rule="naive", naive_recompute=True)
+        wall_r, phases_r = time_steps(ctxn, inputs, dict(out), K, args.naive_steps, 1, torch)
+        ctxn.sync()
+        ctxn.close()
+        naive["recompute_u"] = {"value": updates * args.naive_steps / wall_r,
+                                "ms_per_step": wall_r / args.naive_steps * 1e3,
+                                "iterate_us": phases_r["iterate"]}
     first = None
     if args.naive_steps > 0 and max(Js) <= 4096:
         # the paper's first-stage rule (Algorithm 1) on the same step, for the three-way comparison

@@ -98,6 +98,14 @@ typedef enum { RCSCM_LAMSUM_F64 = 0, RCSCM_LAMSUM_KAHAN32 = 1 } rcscm_lamsum;
 #define RCSCM_FLAG_RUN_ONLY    4u  /* rcscm_run stores its results in the caller's
                                       arrays only and keeps no state (see rcscm_run);
                                       not with RCSCM_FLAG_CHECKPOINT                */
+#define RCSCM_FLAG_NAIVE_RECOMPUTE 8u /* naive rule only: the second launch of an
+                                      iteration recomputes U^ (eq. (16)) from x
+                                      instead of reading it back packed; same
+                                      results bit for bit, 4 B per bin of workspace
+                                      instead of 4 M^2, but slower on MI355X
+                                      (I=513 J=1000 K=20: 1.10x the time at M=2,
+                                      1.23x at M=4, 1.62x at M=8), so the stored
+                                      form is the default                          */
 
 typedef struct {
   double alpha;    /* inverse-gamma shape; default 1.1 (Table 2); needs alpha+2 > 0 */

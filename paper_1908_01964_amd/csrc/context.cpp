@@ -277,8 +277,13 @@ static rcscm_status validate(int U, int I, const int* J, const int* M, const rcs
     *msg = "chunk must be 0, 256, 512, 1024 or 2048";
     return RCSCM_EINVAL;
   }
-  if (p->flags & ~(RCSCM_FLAG_GRAPH | RCSCM_FLAG_CHECKPOINT | RCSCM_FLAG_RUN_ONLY)) {
+  if (p->flags & ~(RCSCM_FLAG_GRAPH | RCSCM_FLAG_CHECKPOINT | RCSCM_FLAG_RUN_ONLY |
+                   RCSCM_FLAG_NAIVE_RECOMPUTE)) {
     *msg = "unknown flag bits";
+    return RCSCM_EINVAL;
+  }
+  if ((p->flags & RCSCM_FLAG_NAIVE_RECOMPUTE) && p->rule != RCSCM_RULE_NAIVE) {
+    *msg = "RCSCM_FLAG_NAIVE_RECOMPUTE applies to the naive rule only";
     return RCSCM_EINVAL;
   }
   if ((p->flags & RCSCM_FLAG_CHECKPOINT) && (p->flags & RCSCM_FLAG_RUN_ONLY)) {
@@ -513,6 +518,7 @@ static rcscm_status alloc_workspace(rcscm_ctx* c) {
   if (c->p.rule == RCSCM_RULE_NAIVE) {
     long long maxMM = 0;
     for (int u = 0; u < c->U; ++u) maxMM = c->M[u] * c->M[u] > maxMM ? c->M[u] * c->M[u] : maxMM;
+    if (c->p.flags & RCSCM_FLAG_NAIVE_RECOMPUTE) maxMM = 1;  // r~h only
     RCSCM_TRY(c->alloc(&c->d_uhat, (size_t)(maxMM * c->nbins), "packed U^"));
   }
   return RCSCM_OK;
@@ -560,7 +566,8 @@ size_t rcscm_workspace_bytes(int U, int I, const int* J, const int* M,
   b += n1(bins) * (sizeof(float4) + 3 * sizeof(float));
   b += 2 * n1(rows) * sizeof(float) + 2 * n1(chunks) * sizeof(uint64_t);
   b += n1(rows) * sizeof(unsigned) + n1(chunks) * sizeof(unsigned) + n1(chunks) * sizeof(double);
-  if (p.rule == RCSCM_RULE_NAIVE) b += n1(maxMM * bins) * sizeof(float);
+  if (p.rule == RCSCM_RULE_NAIVE)
+    b += n1((p.flags & RCSCM_FLAG_NAIVE_RECOMPUTE ? 1 : maxMM) * bins) * sizeof(float);
   return b;
 }
 
@@ -715,11 +722,12 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
     return RCSCM_OK;
   }
   if (c->p.rule == RCSCM_RULE_NAIVE) {
+    const bool store_u = (c->p.flags & RCSCM_FLAG_NAIVE_RECOMPUTE) == 0;
     for (int k = 0; k < K; ++k) {
       for (int m = 2; m <= RCSCM_MAX_M; ++m) {
         const auto rg = c->m_range[m];
         if (rg.second == 0) continue;
-        launch_naive_a(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rsf,
+        launch_naive_a(s, m, store_u, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rsf,
                        c->x_borrowed, c->d_rh, c->d_ru, c->d_lam[c->lam_cur], c->d_uhat, c->nbins,
                        c->d_part[0], alpha, beta, c->d_status);
         RCSCM_HIP(c, hipGetLastError());
@@ -727,11 +735,18 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
       for (int m = 2; m <= RCSCM_MAX_M; ++m) {
         const auto rg = c->m_range[m];
         if (rg.second == 0) continue;
-        launch_naive_b(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rcd,
-                       c->d_part[0], c->d_lam[c->lam_cur], c->d_ru, c->d_uhat, c->nbins,
-                       c->d_status);
+        if (store_u)
+          launch_naive_b(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows, c->d_rcd,
+                         c->d_part[0], c->d_lam[c->lam_cur], c->d_ru, c->d_uhat, c->nbins,
+                         c->d_status);
+        else  // lambda~ stays readable until every chunk has rebuilt R~: new lambda to the other buffer
+          launch_naive_b_recompute(s, m, rg.second, c->d_chunks_m + rg.first, c->d_rows,
+                                   c->d_rsf, c->d_rcd, c->d_part[0], c->d_lam[c->lam_cur],
+                                   c->d_lam[c->lam_cur ^ 1], c->x_borrowed, c->d_uhat, c->d_ru,
+                                   c->d_status);
         RCSCM_HIP(c, hipGetLastError());
       }
+      if (!store_u) c->lam_cur ^= 1;
     }
     return RCSCM_OK;
   }

@@ -170,14 +170,21 @@ void launch_objective(hipStream_t s, int nchunks, const ChunkInfo* chunks, const
                       const float* nu, const float* rh, const float* ru, const float* lam,
                       double alpha, double beta, double* partial);
 
-// NAIVE rule, one iteration = phase A launch + phase B launch per M class.
-void launch_naive_a(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
+// NAIVE rule, one iteration = phase A launch + phase B launch per M class;
+// U^ stored packed between them (store_u), or recomputed by the second launch
+// (launch_naive_b_recompute; uhat then holds r~h, nbins floats).
+void launch_naive_a(hipStream_t s, int M, bool store_u, int nchunks, const ChunkInfo* chunks,
                     const RowInfo* rows, const RowSpatialF* rsf, const float2* x, float* rh,
                     const float* ru, const float* lam, float* uhat, long long nbins,
                     uint64_t* part, float alpha, float beta, unsigned* status);
 void launch_naive_b(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
                     const RowInfo* rows, const RowConstD* rcd, const uint64_t* part, float* lam,
                     float* ru, const float* uhat, long long nbins, unsigned* status);
+void launch_naive_b_recompute(hipStream_t s, int M, int nchunks, const ChunkInfo* chunks,
+                              const RowInfo* rows, const RowSpatialF* rsf, const RowConstD* rcd,
+                              const uint64_t* part, const float* lam_old, float* lam_new,
+                              const float2* x, const float* rh_old, float* ru,
+                              unsigned* status);
 
 // FIRST-STAGE rule (Algorithm 1): one workgroup of 256 lanes per row, x in
 // registers; bpl = first_stage_bpl(J) in {1, 2, 4, 8, 16} (-1: row too long).

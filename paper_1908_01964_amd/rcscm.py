@@ -26,6 +26,7 @@ LAMSUMS = {"f64": 0, "kahan32": 1}
 FLAG_GRAPH = 1
 FLAG_CHECKPOINT = 2
 FLAG_RUN_ONLY = 4
+FLAG_NAIVE_RECOMPUTE = 8
 
 
 class RcscmError(RuntimeError):
@@ -129,7 +130,7 @@ def workspace_bytes(I: int, Js: Sequence[int], Ms: Sequence[int], **kw) -> int:
 
 def _params(alpha=1.1, beta=1e-16, rh0=1.0, ru0=1.0, lam0=1.0, rule="accel", schedule="auto",
             lamsum="f64", block=0, chunk=0, graph=False, checkpoint=False,
-            run_only=False) -> Params:
+            run_only=False, naive_recompute=False) -> Params:
     p = default_params()
     p.alpha, p.beta = float(alpha), float(beta)
     p.rh0, p.ru0, p.lam0 = float(rh0), float(ru0), float(lam0)
@@ -138,7 +139,8 @@ def _params(alpha=1.1, beta=1e-16, rh0=1.0, ru0=1.0, lam0=1.0, rule="accel", sch
     p.lamsum = LAMSUMS[lamsum] if isinstance(lamsum, str) else int(lamsum)
     p.block, p.chunk = int(block), int(chunk)
     p.flags = ((FLAG_GRAPH if graph else 0) | (FLAG_CHECKPOINT if checkpoint else 0)
-               | (FLAG_RUN_ONLY if run_only else 0))
+               | (FLAG_RUN_ONLY if run_only else 0)
+               | (FLAG_NAIVE_RECOMPUTE if naive_recompute else 0))
     return p
 
 

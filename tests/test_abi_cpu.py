@@ -54,6 +54,7 @@ def _create(I=4, J=16, M=4, **kw):
     (dict(rule="first", J=5000), R.ESHAPE, "FIRST"),
     (dict(rule=3), R.EINVAL, "rule"),
     (dict(run_only=True, checkpoint=True), R.EINVAL, "RUN_ONLY"),
+    (dict(naive_recompute=True), R.EINVAL, "naive rule only"),
 ])
 def test_create_rejects_bad_arguments_on_host(kw, status, msg):
     st, err = _create(**kw)
@@ -132,11 +133,13 @@ _RCD = -(-(2 * 64 * 16 + 3 * 8 * 16 + 16 + 3 * 8) // 16) * 16
 _RSF = 2 * 8 * 8 + 64 * 8
 
 
-def _expected_workspace(I, Js, Ms, rule="accel", chunk=0, schedule="auto", checkpoint=False):
+def _expected_workspace(I, Js, Ms, rule="accel", chunk=0, schedule="auto", checkpoint=False,
+                        naive_recompute=False):
     """Every buffer rcscm_create allocates, counted from the allocation list: row, chunk,
     chunk-by-M, row-list and row-by-M tables; three row-constant records; per bin tau^ax,
     sigma^bx (float4), nu, r^h, r^u; lambda and the chunk partial sums twice; row and chunk
-    status words; objective partials; packed U^ (M^2 floats per bin, naive rule)."""
+    status words; objective partials; packed U^ (M^2 floats per bin, naive rule), or r~h
+    (one float per bin) when the naive rule recomputes U^."""
     ck = chunk or 512
     rows = len(Js) * I
     bins = sum(I * j for j in Js)
@@ -151,7 +154,7 @@ def _expected_workspace(I, Js, Ms, rule="accel", chunk=0, schedule="auto", check
     b += rows * (_RCD + _RCF + _RSF) + bins * (16 + 3 * 4)
     b += 2 * rows * 4 + 2 * chunks * 8 + rows * 4 + chunks * 4 + chunks * 8
     if rule == "naive":
-        b += max(m * m for m in Ms) * bins * 4
+        b += (1 if naive_recompute else max(m * m for m in Ms)) * bins * 4
     return b
 
 
@@ -160,6 +163,7 @@ def _expected_workspace(I, Js, Ms, rule="accel", chunk=0, schedule="auto", check
     (513, [1000], [4], dict(chunk=512)),
     (513, [1000], [4], dict(chunk=1024)),
     (513, [1000], [4], dict(rule="naive")),
+    (513, [1000], [4], dict(rule="naive", naive_recompute=True)),
     (513, [1000], [4], dict(rule="first")),
     (513, [1000], [4], dict(schedule="stream")),
     (1025, [8000], [8], dict(checkpoint=True)),

@@ -56,6 +56,22 @@ def test_naive_vs_oracle(M):
     assert_close(out, ref, what=f"naive M={M}")
 
 
+def test_naive_recompute_equals_stored_u():
+    """The naive rule with U^ recomputed in the second launch (RCSCM_FLAG_NAIVE_RECOMPUTE)
+    gives the stored form's results bit for bit: same E-step, same trace order.  A ragged
+    batch of mixed M with an odd number of iterations (the recompute form swaps its lambda
+    buffers every iteration)."""
+    probs = [make_problem(m, 5, j, config=480 + m, utterance=u, spatial="random")
+             for u, (j, m) in enumerate([(300, 2), (777, 4), (129, 8), (513, 5)])]
+    a = gpu_run(probs, 7, rule="naive")
+    b = gpu_run(probs, 7, rule="naive", naive_recompute=True)
+    for u, (ra, rb) in enumerate(zip(a, b)):
+        for k in ra:
+            assert np.array_equal(ra[k], rb[k]), (u, k)
+    ref = oracle_naive(probs[1], 7)
+    assert_close(b[1], ref, what="naive recompute M=4")
+
+
 def test_naive_config0(c0):
     ref = oracle_naive(c0, 20)
     out = gpu_run(c0, 20, rule="naive")[0]
