@@ -87,10 +87,15 @@ typedef enum { RCSCM_SCHED_AUTO = 0, RCSCM_SCHED_STREAM = 1, RCSCM_SCHED_RESIDEN
 
 /* How the per-frequency sum over frames for lambda (eqs. (18), (43), (55)) is
  * accumulated by the accelerated rule.  F64: each lane adds its (at most 16)
- * terms in float, lanes and waves are combined in double in a fixed order
- * (relative error about 1e-6 at worst; reproducible run to run).  KAHAN32:
- * Kahan-compensated float per lane, then a compensated (TwoSum) float tree.
- * The naive and first-stage rules sum in double throughout. */
+ * terms in float; in the RESIDENT schedule and rcscm_run's fused launch the
+ * 64 lanes of a wave are then added in float by a fixed six-level tree and
+ * the waves combined in double (relative error at most (bins per lane + 5) u,
+ * u = 2^-24, for these non-negative terms: below 1.3e-6); the STREAM schedule
+ * combines lanes, waves and chunks in double.  Either way the order is fixed,
+ * so results repeat bit for bit run to run.  KAHAN32: Kahan-compensated float
+ * per lane, then a compensated (TwoSum) float tree (RESIDENT and STREAM only:
+ * rcscm_run then makes the three calls).  The naive and first-stage rules sum
+ * in double throughout. */
 typedef enum { RCSCM_LAMSUM_F64 = 0, RCSCM_LAMSUM_KAHAN32 = 1 } rcscm_lamsum;
 
 #define RCSCM_FLAG_GRAPH       1u  /* capture the STREAM K loop in a hipGraph      */

@@ -1,6 +1,6 @@
 """Builds librcscm.so (HIP kernels for gfx950 + the C ABI) in-tree.
 
-    python -m paper_1908_01964_amd.build [--jobs N] [--verbose]
+    python -m paper_1908_01964_amd.build [--jobs N] [--verbose] [--debug]
 
 Every .hip and .cpp file under csrc/ is compiled with hipcc for
 --offload-arch=gfx950 into _build/, then linked into
@@ -8,6 +8,11 @@ paper_1908_01964_amd/librcscm.so.  Packed-FP32 instructions are disabled
 (-Xclang -target-feature -Xclang -packed-fp32-ops) for all device code.
 Then the plain-C ABI client of the tests (tests/c/abi_run.c) is built
 against the library.
+
+--debug builds _build/debug/librcscm_debug.so instead, with -DRCSCM_DEBUG:
+the kernels check their row, chunk and bin indexes against the extents of
+the arrays they address (RCSCM_DASSERT) and stop with a message on the first
+failed check.  Nothing loads it by default; the CPU tests only compile it.
 """
 import argparse
 import concurrent.futures as cf
@@ -37,9 +42,13 @@ def hipcc():
     raise RuntimeError("hipcc not found (ROCm is required to build librcscm)")
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + COMMON + ["-c", src, "-o", obj]
+DEBUG_BUILD = os.path.join(BUILD, "debug")
+DEBUG_LIB = os.path.join(DEBUG_BUILD, "librcscm_debug.so")
+
+
+def _compile(src, verbose, debug=False):
+    obj = os.path.join(DEBUG_BUILD if debug else BUILD, os.path.basename(src) + ".o")
+    cmd = [hipcc()] + COMMON + (["-DRCSCM_DEBUG"] if debug else []) + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,12 +59,18 @@ def _compile(src, verbose):
     return obj
 
 
-def build(jobs=None, verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs=None, verbose=False, debug=False):
+    os.makedirs(DEBUG_BUILD if debug else BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, debug), srcs))
+    if debug:
+        cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", DEBUG_LIB] + objs
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
+        return DEBUG_LIB
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -91,5 +106,6 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--debug", action="store_true", help="the bounds-checked build (-DRCSCM_DEBUG)")
     a = ap.parse_args()
-    print(build(a.jobs, a.verbose))
+    print(build(a.jobs, a.verbose, a.debug))

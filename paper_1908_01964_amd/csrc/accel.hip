@@ -41,6 +41,8 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
   const int J = ri.J;
   const long long base = ri.bin_off;
   const int t = threadIdx.x;
+  RCSCM_DASSERT(J >= 1 && J <= NT * BPL);
+  RCSCM_DASSERT(ck_rh == nullptr || (base + J <= ck_sb && row < ck_sr));
 
   float4 ts[BPL];
   float vnu[BPL], vrh[BPL], vru[BPL];
@@ -175,6 +177,8 @@ __global__ __launch_bounds__(kStreamNT) void accel_stream_kernel(
   const int len = ck.len;
   const int t = threadIdx.x;
   const int wave = t >> 6;
+  RCSCM_DASSERT(ck.start >= 0 && ck.len >= 1 && ck.start + ck.len <= ri.J);
+  RCSCM_DASSERT(len <= BPL * kStreamNT);
   const double invJ = 1.0 / (double)ri.J;
   __shared__ uint64_t red[NW];
 
@@ -292,6 +296,7 @@ __global__ __launch_bounds__(256) void extract_kernel(
   const RowConstF rc = rcf[ck.row];
   const float lam = lam_in[ck.row];
   const LamTerms L = lam_terms(rc, lam);
+  RCSCM_DASSERT(ck.start >= 0 && ck.len >= 1 && ck.start + ck.len <= ri.J);
   if (lam_out != nullptr && ck.start == 0 && threadIdx.x == 0) lam_out[ck.row] = lam;
 #pragma unroll 4
   for (int jj = threadIdx.x; jj < ck.len; jj += 256) {

@@ -102,6 +102,8 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
   const int J = ri.J;
   const long long base = ri.bin_off;
   const int t = threadIdx.x;
+  RCSCM_DASSERT(J >= 1 && J <= NT * BPL);
+  RCSCM_DASSERT(K == 0 || (base + J <= sb && row < sr));
   const float S2 = rc.sab2, sr_ = rc.sab_re, si_ = rc.sab_im, taa = rc.t_aa;
   const float invM = rc.invM;
   __shared__ uint64_t red[2][NT / 64];

@@ -646,6 +646,8 @@ rcscm_status rcscm_init(rcscm_ctx* c, const void* x, const void* a, const void* 
   A.lam = c->d_lam[c->lam_cur];
   A.status = c->d_status;
   A.chunk_status = c->d_chunk_status;
+  A.n_bins = c->nbins;
+  A.n_rows = c->nrows;
   for (int m = 2; m <= RCSCM_MAX_M; ++m) {
     const auto rg = c->m_range[m];
     if (rg.second == 0) continue;
@@ -1027,6 +1029,8 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
   A.inv_a2 = (float)(1.0 / (c->p.alpha + 2.0));
   A.beta_a2 = (float)(c->p.beta / (c->p.alpha + 2.0));
   A.K = K;
+  A.n_bins = c->nbins;
+  A.n_rows = c->nrows;
   A.ck_rh = A.ck_ru = A.ck_lam = nullptr;
   A.ck_sb = 0;
   A.ck_sr = 0;

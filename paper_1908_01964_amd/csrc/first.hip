@@ -69,6 +69,7 @@ __global__ __launch_bounds__(kFirstNT) void first_stage_kernel(
   const int J = ri.J;
   const long long base = ri.bin_off;
   const int t = threadIdx.x;
+  RCSCM_DASSERT(ri.M == M && J >= 1 && J <= kFirstNT * BPL);
   const double invJ = 1.0 / (double)J;
 
   __shared__ double2 aug[M][2 * M];

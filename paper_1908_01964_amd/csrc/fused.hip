@@ -37,6 +37,10 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
   const int J = ri.J;
   const long long base = ri.bin_off;
   const int t = threadIdx.x;
+  RCSCM_DASSERT(row >= 0 && row < A.n_rows);
+  RCSCM_DASSERT(ri.M == M && J >= 1 && J <= NT * BPL);
+  RCSCM_DASSERT(base >= 0 && base + J <= A.n_bins);
+  RCSCM_DASSERT(A.ck_rh == nullptr || (A.ck_sb >= A.n_bins && A.ck_sr >= A.n_rows));
   __shared__ SetupLDS<M> L;
   __shared__ uint64_t red[2][NW];
   __shared__ unsigned cflag;

@@ -24,6 +24,9 @@ __global__ __launch_bounds__(kInitNT) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int row = ck.row;
   const RowInfo ri = A.rows[row];
   const int t = threadIdx.x;
+  RCSCM_DASSERT(row >= 0 && row < A.n_rows && ri.M == M);
+  RCSCM_DASSERT(ck.start >= 0 && ck.len >= 1 && ck.start + ck.len <= ri.J);
+  RCSCM_DASSERT(ri.bin_off >= 0 && ri.bin_off + ri.J <= A.n_bins);
   __shared__ SetupLDS<M> L;
 
   constexpr int G = M <= 4 ? 4 : (M <= 6 ? 2 : 1);

@@ -166,6 +166,9 @@ __global__ __launch_bounds__(kNT) void naive_a_kernel(
   __shared__ cf sRt[M][M];  // R~ = R' + lambda~ b b^H
   __shared__ cf sa[M], sb[M];
   __shared__ uint64_t red[kNT / 64];
+  RCSCM_DASSERT(ri.M == M);
+  RCSCM_DASSERT(ck.start >= 0 && ck.len >= 1 && ck.start + ck.len <= ri.J);
+  RCSCM_DASSERT(ri.bin_off + ck.start + ck.len <= nbins);
   naive_row_model<M>(rsf + ck.row, lam[ck.row], sRt, sa, sb);
   __syncthreads();
 
@@ -249,6 +252,9 @@ __global__ __launch_bounds__(kNT) void naive_b_kernel(const ChunkInfo* __restric
   const RowInfo ri = rows[ck.row];
   const RowConstD* D = rcd + ck.row;
   const int t = threadIdx.x;
+  RCSCM_DASSERT(ri.M == M);
+  RCSCM_DASSERT(ck.start >= 0 && ck.len >= 1 && ck.start + ck.len <= ri.J);
+  RCSCM_DASSERT(ri.bin_off + ck.start + ck.len <= nbins);
   __shared__ double2 aug[M][2 * M];
   __shared__ float2 sR[M * M];
   const float l = wave_sum_packed<0>(part + ri.part_off, ri.nparts).mean(1.0 / (double)ri.J);
@@ -304,6 +310,8 @@ __global__ __launch_bounds__(kNT) void naive_b_recompute_kernel(
   __shared__ cf sa[M], sb[M];
   __shared__ double2 aug[M][2 * M];
   __shared__ float2 sR[M * M];
+  RCSCM_DASSERT(ri.M == M);
+  RCSCM_DASSERT(ck.start >= 0 && ck.len >= 1 && ck.start + ck.len <= ri.J);
   naive_row_model<M>(rsf + ck.row, lam_old[ck.row], sRt, sa, sb);
   const float l = wave_sum_packed<0>(part + ri.part_off, ri.nparts).mean(1.0 / (double)ri.J);
   if (ck.start == 0 && t == 0) {

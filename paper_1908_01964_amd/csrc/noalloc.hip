@@ -169,6 +169,8 @@ extern "C" rcscm_status rcscm_run_noalloc(int I, int J, int M, const rcscm_param
   A.inv_a2 = (float)(1.0 / (p.alpha + 2.0));
   A.beta_a2 = (float)(p.beta / (p.alpha + 2.0));
   A.K = K;
+  A.n_bins = (long long)I * J;
+  A.n_rows = I;
   launch_fused(st, M, nt, bpl, I, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RCSCM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));

@@ -5,6 +5,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Device-side bounds checks of a debug build (-DRCSCM_DEBUG): a failed check
+// prints where it failed and stops the kernel.  Compiled out otherwise.
+#ifdef RCSCM_DEBUG
+#define RCSCM_DASSERT(cond)                                                        \
+  do {                                                                             \
+    if (!(cond)) {                                                                 \
+      printf("rcscm debug check failed: %s (%s:%d, block %d, thread %d)\n", #cond, \
+             __FILE__, __LINE__, (int)blockIdx.x, (int)threadIdx.x);               \
+      __builtin_trap();                                                            \
+    }                                                                              \
+  } while (0)
+#else
+#define RCSCM_DASSERT(cond) ((void)0)
+#endif
+
 namespace rcscm {
 
 constexpr int MAXM = 8;
@@ -93,6 +108,8 @@ struct InitArgs {
   float* lam;
   unsigned* status;
   unsigned* chunk_status;
+  long long n_bins;  // extent of the per-bin arrays (bounds checks of a debug build)
+  int n_rows;        // extent of the per-row arrays
 };
 void launch_init(hipStream_t s, int M, int nchunks, const InitArgs& args);
 
@@ -136,6 +153,8 @@ struct FusedArgs {
   int ck_sr;
   float inv_a2, beta_a2;
   int K;
+  long long n_bins;  // extent of the per-bin arrays (bounds checks of a debug build)
+  int n_rows;        // extent of the per-row arrays
 };
 bool fused_class(int J, int* nt, int* bpl);
 bool fused_supported(int nt, int bpl);
