@@ -591,6 +591,7 @@ def main():
     # iterate/objective/backward.
     run_us = None
     with_state = None
+    sustained = None
     run_table = best_run_classes(I, Js, Ms, K) if fused else None
     fused_sched = None
     if fused:
@@ -609,6 +610,15 @@ def main():
                       "extra_bytes_per_bin": FUSED_STATE_BYTES_PER_BIN,
                       "note": "rcscm_run on a context that keeps tau^ax, sigma^bx, nu, r^h, r^u "
                               "for later calls"}
+        # Sustained throughput: the same call back to back for about 50 ms of GPU time (at
+        # least 200 calls, at most 0.5 s), reported beside the step; it also brings the GPU to
+        # the clock it holds under continuous load before the timed steps.
+        per_step_s = max(wall_s / wsteps, 1e-6)
+        n_sus = int(min(max(200, 0.05 / per_step_s), max(200, 0.5 / per_step_s)))
+        wall_sus, sus_us = time_run(ctx_ro, inputs, out, K, n_sus, 0, torch)
+        sustained = {"steps": n_sus, "ms_per_step": wall_sus / n_sus * 1e3, "launch_us": sus_us,
+                     "value": updates * n_sus / wall_sus,
+                     "note": "rcscm_run (run-only) back to back, right before the timed steps"}
         wall, run_us = time_run(ctx_ro, inputs, out, K, args.steps, args.warmup, torch)
         ctx_ro.sync()
         ctx_ro.close()
@@ -688,6 +698,8 @@ def main():
     }
     if with_state is not None:
         line["run_with_state"] = with_state
+    if sustained is not None:
+        line["sustained"] = sustained
     if stream is not None:
         line["stream"] = stream
         if stream_hbm is not None:
