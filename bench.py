@@ -386,6 +386,37 @@ def time_backproject(I, J, M, K, steps, torch):
             "backproject_GBps_algorithmic": bytes_bin * nbins / (bp_us * 1e-6) / 1e9}
 
 
+def time_batch(torch, steps=20, warmup=5):
+    """The ragged batch (64 utterances, J in [200, 4000], M in {2, 4, 6}, I=513, K=20) as one
+    rcscm_run per step on a run-only context with the autotuned classes: about 50 ms of calls
+    back to back, then warmup + steps timed as the headline step is."""
+    from paper_1908_01964_amd import Context, to_device
+    from paper_1908_01964_amd.autotune import best_run_classes
+    I, Js, Ms, K, probs, label = load_workload(2)
+    inputs = to_device(probs)
+    del probs
+    nbins = I * sum(Js)
+    dev = inputs[0].device
+    out = dict(rh=torch.empty(nbins, dtype=torch.float32, device=dev),
+               ru=torch.empty(nbins, dtype=torch.float32, device=dev),
+               lam=torch.empty(I * len(Js), dtype=torch.float32, device=dev),
+               s_hat=torch.empty(nbins, dtype=torch.complex64, device=dev))
+    table = best_run_classes(I, Js, Ms, K)
+    ctx = Context(I, Js, Ms, run_only=True, run_classes=table)
+    time_run(ctx, inputs, out, K, 30, 2, torch)
+    wall, launch_us = time_run(ctx, inputs, out, K, steps, warmup, torch)
+    ctx.sync()
+    res = {"workload": label, "bins": nbins, "steps": steps, "warmup": warmup,
+           "value": nbins * K * steps / wall, "ms_per_step": wall / steps * 1e3,
+           "launch_us": launch_us, "call": "rcscm_run (fused; RCSCM_FLAG_RUN_ONLY)",
+           "fused_classes": ctx.run_classes(),
+           "class_source": "autotuned (tune_cache.json)" if table else "built-in table"}
+    ctx.close()
+    del inputs, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def load_workload(wid):
     """(I, Js, Ms, K, problems, label) of a named workload."""
     from synth import WORKLOADS, batch_shapes, batch_utterance, config
@@ -492,6 +523,8 @@ def main():
     ap.add_argument("--naive-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true", help="skip the STREAM-schedule entry")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="workload 1: skip the ragged-batch entry (workload 2's step)")
     ap.add_argument("--cpu-reps", type=int, default=15, help="timed runs of the CPU oracle")
     ap.add_argument("--modular", action="store_true",
                     help="time the step as three calls (init, iterate, extract) instead of run")
@@ -591,6 +624,9 @@ def main():
         stream = time_stream(I, Js, Ms, inputs, K, 5 if args.workload == 1 else 2, torch)
         if args.workload == 1:
             stream_hbm = time_stream_hbm(torch, *inputs[1:])
+    batch = None
+    if args.workload == 1 and not args.no_batch:
+        batch = time_batch(torch)
     fused = args.schedule != "stream" and max(Js) <= 8192 and not args.modular
     msteps = args.steps if not fused else max(10, args.steps // 4)
     out_m = {k: torch.empty_like(v) for k, v in out.items()}
@@ -729,6 +765,8 @@ def main():
         line["run_with_state"] = with_state
     if sustained is not None:
         line["sustained"] = sustained
+    if batch is not None:
+        line["ragged_batch"] = batch
     if stream is not None:
         line["stream"] = stream
         if stream_hbm is not None:
