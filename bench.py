@@ -612,6 +612,22 @@ def main():
         first = {"value": updates * args.naive_steps / wall_f,
                  "ms_per_step": wall_f / args.naive_steps * 1e3, "phases_us": phases_f}
 
+    # The compensated lambda sum (RCSCM_LAMSUM_KAHAN32: Kahan per lane, TwoSum tree), on the
+    # same step as three calls (the fused launch sums with the default policy only).
+    kahan = None
+    if args.workload == 1 and args.naive_steps > 0:
+        ctxk = Context(I, Js, Ms, lamsum="kahan32", **sched)
+        out_k = {k: torch.empty_like(v) for k, v in out.items()}
+        wall_k, phases_k = time_steps(ctxk, inputs, out_k, K, max(10, args.steps // 4), 2, torch)
+        ctxk.sync()
+        kahan = {"value": updates * max(10, args.steps // 4) / wall_k, "phases_us": phases_k,
+                 "schedule": ctxk.schedule(),
+                 "call": "rcscm_init + rcscm_iterate + rcscm_extract (lamsum KAHAN32)"}
+        if ref is not None:
+            st_k = row_error_stats({k: v.cpu().numpy() for k, v in out_k.items()}, ref)
+            kahan["rel_err_vs_fp64"] = dict(st_k["normwise"])
+        ctxk.close()
+
     bp = None
     if args.workload == 1 and args.naive_steps > 0:
         bp = time_backproject(I, Js[0], Ms[0], K, max(10, args.steps // 4), torch)
@@ -781,6 +797,8 @@ def main():
         line["iterate_speedup_vs_first_stage"] = first["phases_us"]["iterate"] / phases["iterate"]
     if bp is not None:
         line["backproject"] = bp
+    if kahan is not None:
+        line["lamsum_kahan32"] = kahan
     if cb is not None:
         line["cpu_baseline"] = cb
         st = row_error_stats(gpu_out, ref)
