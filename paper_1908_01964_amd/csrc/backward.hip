@@ -17,6 +17,14 @@
 //       it completes lambda_bar_{k+1}, which reaches every bin through
 //       lambda_{k+1} = mean_j t_j.
 //   #2: d/d lambda_k of everything computed from it in this iteration.
+// As in the forward kernels, sigma^bx is used turned by the phase p of
+// sigma^ab (u = p sigma^bx, turn_sigma_bx): sigma^ab sigma^bx = |sigma^ab| u
+// and p e = u - |sigma^ab| w, so the recomputed forward and its reverse take
+// real factors where the printed rule has complex ones.  The reverse pass
+// accumulates u_bar; sigma_bar = conj(p) u_bar before x_bar is formed.
+// The two sums of a reversed iteration add a lane's terms and the 64 lanes of
+// a wave in float (a fixed tree, as the forward's frame sum) and the waves in
+// double; the extraction's sum runs in double throughout.
 // At the end x_bar = c tau_bar' + b sigma_bar + 2 nu_bar (R')^+ x with
 // c = (R')^+ a and tau_bar' = tau_bar - 2 tau^ax nu_bar / tau^aa (nu =
 // tau^xx - |tau^ax|^2/tau^aa), in FP64 from the row constants.
@@ -33,6 +41,19 @@ __device__ __forceinline__ double block_sum(double v, uint64_t (*red)[NT / 64], 
   a = wave_allreduce<0>(a);
   const int t = threadIdx.x;
   if ((t & 63) == 0) red[phase & 1][t >> 6] = a.pack();
+  __syncthreads();
+  const double s = slots_sum<0, NT / 64>(red[phase & 1]).s;
+  ++phase;
+  return s;
+}
+
+// Sum over the workgroup of a float per lane: the wave's lanes in float by a
+// fixed tree, the waves in double (one LDS slot each).
+template <int NT>
+__device__ __forceinline__ double block_sum_f32(float v, uint64_t (*red)[NT / 64], int& phase) {
+  v = wave_sum_f32(v);
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) red[phase & 1][t >> 6] = LamAcc<0>::from(v).pack();
   __syncthreads();
   const double s = slots_sum<0, NT / 64>(red[phase & 1]).s;
   ++phase;
@@ -104,26 +125,28 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
   const int t = threadIdx.x;
   RCSCM_DASSERT(J >= 1 && J <= NT * BPL);
   RCSCM_DASSERT(K == 0 || (base + J <= sb && row < sr));
-  const float S2 = rc.sab2, sr_ = rc.sab_re, si_ = rc.sab_im, taa = rc.t_aa;
+  const float S2 = rc.sab2, sab = rc.sab_abs, taa = rc.t_aa;
   const float invM = rc.invM;
   __shared__ uint64_t red[2][NT / 64];
   int phase = 0;
 
   float4 ts[BPL];
+  // Bbr, Bbi: the gradient of the turned u (of sigma^bx only at the end)
   float Tbr[BPL], Tbi[BPL], Bbr[BPL], Bbi[BPL], nub[BPL], hb[BPL], ub[BPL];
 #pragma unroll
   for (int q = 0; q < BPL; ++q) {
     const int j = t + q * NT;
-    ts[q] = (j < J) ? tsig[base + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    ts[q] = (j < J) ? turn_sigma_bx(tsig[base + j], rc) : make_float4(0.f, 0.f, 0.f, 0.f);
     Tbr[q] = Tbi[q] = Bbr[q] = Bbi[q] = nub[q] = hb[q] = ub[q] = 0.f;
   }
 
-  // ---- extraction: s_hat = gamma P, P = T + s B / lambda, gamma = h / (u + h A)
+  // ---- extraction: s_hat = gamma P, P = T + |s| U / lambda, gamma = h / (u + h A)
   float lam_bar;
   {
     const float lam = lam_fin[row];
     const float il = frcp_nr(lam);
     const float A = fmaf(S2, il, taa);
+    const float sil = sab * il;
     double c = 0.0;
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
@@ -132,8 +155,8 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
       const float h = rh_fin[base + j], u = ru_fin[base + j];
       const float2 gs = grad_s[base + j];
       const float4 T = ts[q];
-      const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
-      const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
+      const float Pr = fmaf(sil, T.z, T.x);
+      const float Pi = fmaf(sil, T.w, T.y);
       const float D = fmaf(h, A, u);
       const float iD = frcp(D);
       const float gam = h * iD;
@@ -145,12 +168,11 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
       const float Abar = Dbar * h;
       Tbr[q] += Pbr;
       Tbi[q] += Pbi;
-      // B_bar += conj(s) il P_bar
-      Bbr[q] += il * (sr_ * Pbr + si_ * Pbi);
-      Bbi[q] += il * (sr_ * Pbi - si_ * Pbr);
-      // il_bar += Re(conj(s B) P_bar)
-      const float sBr = sr_ * T.z - si_ * T.w, sBi = sr_ * T.w + si_ * T.z;
-      c += (double)(sBr * Pbr + sBi * Pbi) + (double)(S2 * Abar);
+      // U_bar += |s| il P_bar
+      Bbr[q] += sil * Pbr;
+      Bbi[q] += sil * Pbi;
+      // il_bar += Re(conj(|s| U) P_bar)
+      c += (double)(sab * fmaf(T.z, Pbr, T.w * Pbi)) + (double)(S2 * Abar);
     }
     const double ilbar = block_sum<NT>(c, red, phase);
     lam_bar = (float)(-(double)il * (double)il * ilbar);
@@ -172,6 +194,7 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
     const float lam_n = (k + 1 < K) ? ck_lam[(long long)(k + 1) * sr + row] : lam_fin[row];
     const float il = frcp_nr(lam), il_n = frcp_nr(lam_n);
     const float A = fmaf(S2, il, taa), A_n = fmaf(S2, il_n, taa);
+    const float sil = sab * il;
     float vh[BPL], vu[BPL];
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
@@ -191,19 +214,19 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
     // ones are recomputed there)
     constexpr bool kKeep = BPL <= 4;  // registers allow it up to 4 bins per lane
     float viD[BPL], vg[BPL], vE[BPL];
-    float c1 = 0.0f;  // the lane's terms in float, lanes in double
+    float c1 = 0.0f;  // the lane's terms in float
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
       const int j = t + q * NT;
       const float4 T = ts[q];
       const float h = vh[q], u = vu[q];
-      const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
-      const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
+      const float Pr = fmaf(sil, T.z, T.x);
+      const float Pi = fmaf(sil, T.w, T.y);
       const float iD = frcp(fmaf(h, A, u));
       const float g = h * iD;
       const float wr = g * Pr, wi = g * Pi;
-      const float er = T.z - (sr_ * wr + si_ * wi), ei = T.w - (sr_ * wi - si_ * wr);
-      const float E = er * er + ei * ei;
+      const float er = fmaf(-sab, wr, T.z), ei = fmaf(-sab, wi, T.w);
+      const float E = fmaf(er, er, ei * ei);
       if constexpr (kKeep) {
         viD[q] = iD;
         vg[q] = g;
@@ -211,7 +234,7 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
       }
       if (j < J) c1 += ub[q] * invM * fmaf(S2, g * u, E);
     }
-    const double ilnbar = block_sum<NT>((double)c1, red, phase);
+    const double ilnbar = block_sum_f32<NT>(c1, red, phase);
     const float lam_n_bar = (float)((double)lam_bar - (double)il_n * (double)il_n * ilnbar);
     const float tbar = lam_n_bar * rc.invJ;
 
@@ -221,15 +244,15 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
       const int j = t + q * NT;
       const float4 T = ts[q];
       const float h = vh[q], u = vu[q];
-      const float Pr = T.x + il * (sr_ * T.z - si_ * T.w);
-      const float Pi = T.y + il * (sr_ * T.w + si_ * T.z);
+      const float Pr = fmaf(sil, T.z, T.x);
+      const float Pi = fmaf(sil, T.w, T.y);
       const float iD = kKeep ? viD[q] : frcp(fmaf(h, A, u));
       const float g = kKeep ? vg[q] : h * iD;
       const float iu = frcp(u);
       const float R2 = Pr * Pr + Pi * Pi;
       const float Q = fmaf(g, R2, u);
       const float wr = g * Pr, wi = g * Pi;
-      const float er = T.z - (sr_ * wr + si_ * wi), ei = T.w - (sr_ * wi - si_ * wr);
+      const float er = fmaf(-sab, wr, T.z), ei = fmaf(-sab, wi, T.w);
       const float E = kKeep ? vE[q] : fmaf(er, er, ei * ei);
       const float dr = T.x - wr * taa, di = T.y - wi * taa;
       // r^u_{k+1} = (g u A_n + nu + |d|^2 / taa + E / lambda_n) / M
@@ -248,12 +271,12 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
       Tbr[q] += dbr;
       Tbi[q] += dbi;
       float wbr = -taa * dbr, wbi = -taa * dbi;
-      // E = |e|^2 ; e = B - conj(s) w
+      // E = |e|^2 ; p e = U - |s| w
       const float ebr = 2.0f * er * Ebar, ebi = 2.0f * ei * Ebar;
       Bbr[q] += ebr;
       Bbi[q] += ebi;
-      wbr -= sr_ * ebr - si_ * ebi;
-      wbi -= sr_ * ebi + si_ * ebr;
+      wbr = fmaf(-sab, ebr, wbr);
+      wbi = fmaf(-sab, ebi, wbi);
       // w = g P
       gbar += Pr * wbr + Pi * wbi;
       float Pbr = g * wbr, Pbi = g * wbi;
@@ -271,21 +294,36 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
       const float Dbar = -gbar * g * iD;
       ubar += Dbar;
       hbar += Dbar * A;
-      // P = T + s B il
+      // P = T + |s| il U
       Tbr[q] += Pbr;
       Tbi[q] += Pbi;
-      Bbr[q] += il * (sr_ * Pbr + si_ * Pbi);
-      Bbi[q] += il * (sr_ * Pbi - si_ * Pbr);
-      const float sBr = sr_ * T.z - si_ * T.w, sBi = sr_ * T.w + si_ * T.z;
-      if (j < J) c2 += sBr * Pbr + sBi * Pbi + S2 * Dbar * h;
+      Bbr[q] = fmaf(sil, Pbr, Bbr[q]);
+      Bbi[q] = fmaf(sil, Pbi, Bbi[q]);
+      if (j < J) c2 += fmaf(sab, fmaf(T.z, Pbr, T.w * Pbi), S2 * Dbar * h);
       hb[q] = hbar;
       ub[q] = ubar;
     }
-    const double ilbar = block_sum<NT>((double)c2, red, phase);
+    const double ilbar = block_sum_f32<NT>(c2, red, phase);
     lam_bar = (float)(-(double)il * (double)il * ilbar);
   }
 
   if (t == 0 && grad_lam0 != nullptr) grad_lam0[row] = lam_bar;
+
+  // sigma_bar = conj(p) u_bar, p = sigma^ab / |sigma^ab| (1 when sigma^ab = 0)
+  {
+    float pr = 1.0f, pi = 0.0f;
+    if (sab > 0.0f) {
+      const float ia = 1.0f / sab;
+      pr = rc.sab_re * ia;
+      pi = rc.sab_im * ia;
+    }
+#pragma unroll
+    for (int q = 0; q < BPL; ++q) {
+      const float ur = Bbr[q], ui = Bbi[q];
+      Bbr[q] = fmaf(pr, ur, pi * ui);
+      Bbi[q] = fmaf(pr, ui, -pi * ur);
+    }
+  }
 
   // ---- precomputation: x_bar = c T_bar' + b B_bar + 2 nu_bar (R')^+ x
   const RowConstD* Dc = rcd + row;
