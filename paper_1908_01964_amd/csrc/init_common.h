@@ -10,7 +10,8 @@
 //   4. A = R' + s b b^H with s = tr(R')/(M-1) is Hermitian positive definite
 //      and, because R' b = 0 and ||b|| = 1, A^{-1} = (R')^+ + b b^H / s -
 //      the pseudoinverse expansion of eq. (26) with lambda = s.  A^{-1} comes
-//      from a lane-parallel Gauss-Jordan elimination (M steps), so
+//      from an LDL^H factorisation in registers for M <= 4, else from a
+//      lane-parallel Gauss-Jordan elimination (M steps), so
 //      (R')^+ = A^{-1} - b b^H / s and log pdet(R') = log det A - log s;
 //   5. c = (R')^+ a, tau^(aa) = a^H c, sigma^(ab) = a^H b.
 // Precomputation of one bin (eqs. (33), (47), (48)), in FP64 from the
