@@ -64,11 +64,21 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "accel_fused_sinc_M4_I513_J1000_K2
 VALU_FILE = os.path.join(ROOT, "profiles", "accel_fused_sinc_M4_I513_J1000_K20_valu.json")
 
 
+def _code_only(src):
+    """C/C++ source without comments and blank space, so that edits of comments alone do not
+    count as a change of the kernel (string literals in these sources hold no comment markers)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_sha():
+    """Hash of the dominant kernel's sources, comments and spacing left out."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
