@@ -28,8 +28,12 @@ def _sample_rows(Js, n=16, seed=0):
 def test_config2_full_batch_sampled_rows(batch, schedule):
     Js, Ms, probs = batch
     K = 20
-    if schedule == "fused":  # rcscm_run: one launch per class, classes spread over streams
-        outs = gpu_run(probs, K, fused=True)
+    if schedule == "fused":
+        # the bench step: rcscm_run on a run-only context with the autotuned classes, one launch
+        # per class, the classes spread over the library's streams
+        from paper_1908_01964_amd.autotune import best_run_classes
+        outs = gpu_run(probs, K, fused=True, run_only=True,
+                       run_classes=best_run_classes(513, Js, Ms, K))
     else:
         outs = gpu_run(probs, K, schedule=schedule)
     got = {k: [] for k in ("rh", "ru", "lam", "s_hat")}
@@ -66,8 +70,8 @@ def test_config4_full_size_subsample():
     sub = config(4, freqs=sel)
     ref = oracle_accel(sub, K)
     for schedule in ("resident", "stream", "fused"):
-        if schedule == "fused":  # the bench step: accel_fused_kernel<8, 1024, 8>
-            out = gpu_run(p, K, fused=True)[0]
+        if schedule == "fused":  # the bench step: accel_fused_kernel<8, 1024, 8>, run-only
+            out = gpu_run(p, K, fused=True, run_only=True)[0]
         else:
             out = gpu_run(p, K, schedule=schedule)[0]
         got = {k: v[sel] for k, v in out.items()}
