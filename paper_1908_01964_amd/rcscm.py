@@ -161,6 +161,10 @@ class Context:
         self.params = _params(**params)
         self.nbins = sum(self.I * j for j in self.Js)
         self.nrows = self.U * self.I
+        # element counts of x, a (and b) and Rp in the batch layout, checked at every call
+        self._nx = sum(self.I * j * m for j, m in zip(self.Js, self.Ms))
+        self._na = sum(self.I * m for m in self.Ms)
+        self._nr = sum(self.I * m * m for m in self.Ms)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             if self.U == 1:
@@ -340,9 +344,7 @@ class Context:
 
     # -- helpers -----------------------------------------------------------------------------
     def _check_sizes(self, x, a, Rp, b, rh0, ru0, lam0):
-        nx = sum(self.I * j * m for j, m in zip(self.Js, self.Ms))
-        na = sum(self.I * m for m in self.Ms)
-        nr = sum(self.I * m * m for m in self.Ms)
+        nx, na, nr = self._nx, self._na, self._nr
         for t, n, dt, name in ((x, nx, torch.complex64, "x"), (a, na, torch.complex128, "a"),
                                (Rp, nr, torch.complex128, "Rp"), (b, na, torch.complex128, "b")):
             if t.dtype != dt or t.numel() != n:
