@@ -102,9 +102,11 @@ __device__ __forceinline__ float4 turn_sigma_bx(const float4 ts, const RowConstF
 // quantities as phase_a with
 //   rho~ax = tau^ax + (|sigma^ab| / lambda~) u,
 //   |e| = |u - |sigma^ab| w|.
+// sab2 is |sigma^ab|^2 of the row, or 0 for a padding bin (ts = 0), whose t
+// is then exactly 0 as long as r~h and r~u are finite and r~u > 0.
 __device__ __forceinline__ PhaseA phase_a_turned(const float4 ts, float rh, float ru,
                                                  const RowConstF& rc, const LamTerms& Lt,
-                                                 float inv_a2, float beta_a2) {
+                                                 float inv_a2, float beta_a2, float sab2) {
   PhaseA o;
   const float rx_re = fmaf(Lt.sa_il, ts.z, ts.x);
   const float rx_im = fmaf(Lt.sa_il, ts.w, ts.y);
@@ -116,7 +118,7 @@ __device__ __forceinline__ PhaseA phase_a_turned(const float4 ts, float rh, floa
   const float e_re = fmaf(-rc.sab_abs, o.w_re, ts.z);
   const float e_im = fmaf(-rc.sab_abs, o.w_im, ts.w);
   o.E = fmaf(e_re, e_re, e_im * e_im);
-  o.t = fmaf(g, rc.sab2, o.E * frcp(ru));
+  o.t = fmaf(g, sab2, o.E * frcp(ru));
   return o;
 }
 
@@ -231,22 +233,23 @@ __device__ __forceinline__ float readlane_f32(float v, int lane) {
 
 constexpr int kRowRor8 = 0x128, kRowRor4 = 0x124, kRowRor2 = 0x122, kRowRor1 = 0x121;
 
-// Sum of a float over the 64 lanes of a wave by a fixed tree, the same value
-// in every lane: DPP row rotations by 8, 4, 2, 1 leave each 16-lane row's sum
-// in all its lanes; swapping the 32-lane halves adds rows 0 + 2 and 1 + 3,
-// swapping neighbouring rows adds those two.  For non-negative terms the
-// relative error is at most 6 u.
-__device__ __forceinline__ float wave_sum_f32(float v) {
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+// Sum of a float over the 64 lanes of a wave by a fixed tree, left in lane 63
+// only: the row rotations by 8, 4, 2, 1 leave each 16-lane row's sum in all
+// its lanes; adding lane 15 of every row into the next row leaves rows 2 + 3
+// in row 3 and rows 0 + 1 in row 1, and adding lane 31 into rows 2 and 3 then
+// leaves the total in row 3 (the other rows hold partial sums, unused).  Six
+// additions folded with their lane moves, no lane swaps.  For non-negative
+// terms the relative error is at most 6 u.
+__device__ __forceinline__ float wave_sum_f32_last(float v) {
   v += dpp_f32_add_src<kRowRor8>(v);
   v += dpp_f32_add_src<kRowRor4>(v);
   v += dpp_f32_add_src<kRowRor2>(v);
   v += dpp_f32_add_src<kRowRor1>(v);
-  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false,
-                                                  false);
-  v = __int_as_float(h[0]) + __int_as_float(h[1]);
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false,
-                                                  false);
-  return __int_as_float(r[0]) + __int_as_float(r[1]);
+  v += dpp_f32_add_src<kRowBcast15>(v);
+  v += dpp_f32_add_src<kRowBcast31>(v);
+  return v;
 }
 
 template <int LS, int CTRL>

@@ -51,9 +51,9 @@ __device__ __forceinline__ double block_sum(double v, uint64_t (*red)[NT / 64], 
 // fixed tree, the waves in double (one LDS slot each).
 template <int NT>
 __device__ __forceinline__ double block_sum_f32(float v, uint64_t (*red)[NT / 64], int& phase) {
-  v = wave_sum_f32(v);
+  v = wave_sum_f32_last(v);
   const int t = threadIdx.x;
-  if ((t & 63) == 0) red[phase & 1][t >> 6] = LamAcc<0>::from(v).pack();
+  if ((t & 63) == 63) red[phase & 1][t >> 6] = LamAcc<0>::from(v).pack();
   __syncthreads();
   const double s = slots_sum<0, NT / 64>(red[phase & 1]).s;
   ++phase;

@@ -25,9 +25,17 @@ __device__ __forceinline__ float resident_loop(
   const int t = threadIdx.x;
   const int wave = t >> 6;
   const double invJ = 1.0 / (double)J;
-  float nuM[BPL];  // nu / M, the form phase B takes
+  // nu / M, the form phase B takes, and |sigma^ab|^2 per bin.  A padding bin
+  // (frame t + q*NT >= J, ts = 0) takes 0 for the latter, so its lambda term
+  // is exactly 0 and it needs no mask in the frame sum, and 1 for the former,
+  // which keeps its r^u >= 1 and so its reciprocal finite in every iteration.
+  float nuM[BPL], sab2q[BPL];
 #pragma unroll
-  for (int q = 0; q < BPL; ++q) nuM[q] = vnu[q] * rc.invM;
+  for (int q = 0; q < BPL; ++q) {
+    const bool in = t + q * NT < J;
+    nuM[q] = in ? vnu[q] * rc.invM : 1.0f;
+    sab2q[q] = in ? rc.sab2 : 0.0f;
+  }
   LamTerms Lt = lam_terms(rc, lam_t);
   for (int k = 0; k < K; ++k) {
     if (CK && ck_rh != nullptr) {  // checkpoint theta at the start of iteration k
@@ -46,19 +54,17 @@ __device__ __forceinline__ float resident_loop(
     float tsum;  // F64 policy: the lane's <= BPL terms in float
 #pragma unroll
     for (int q = 0; q < BPL; ++q) {
-      A[q] = phase_a_turned(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2);
-      const bool in = t + q * NT < J;
+      A[q] = phase_a_turned(ts[q], vrh[q], vru[q], rc, Lt, inv_a2, beta_a2, sab2q[q]);
       if constexpr (LS == 0) {
-        const float tq = in ? A[q].t : 0.0f;
-        tsum = q == 0 ? tq : tsum + tq;
-      } else if (in) {
+        tsum = q == 0 ? A[q].t : tsum + A[q].t;
+      } else if (t + q * NT < J) {
         acc.add(A[q].t);
       }
       vrh[q] = A[q].rh_new;
     }
     if constexpr (LS == 0) {
-      const float v = wave_sum_f32(tsum);
-      if ((t & 63) == 0) red[k & 1][wave] = LamAcc<0>::from(v).pack();
+      const float v = wave_sum_f32_last(tsum);
+      if ((t & 63) == 63) red[k & 1][wave] = LamAcc<0>::from(v).pack();
     } else {
       acc = wave_allreduce<LS>(acc);
       if ((t & 63) == 0) red[k & 1][wave] = acc.pack();
