@@ -149,7 +149,8 @@ rcscm_status rcscm_create_batch(rcscm_ctx** out, int U, int I, const int* J, con
 /* Per-frequency setup and per-bin precomputation (Algorithm 2, before the
  * loop; eqs. (32), (33), (46)-(48) and the pseudoinverse of eq. (26)):
  *   - b is normalised and R' projected onto the orthogonal complement of b,
- *     in FP64; (R')^+ = (R' + s b b^H)^{-1} - b b^H / s with s = tr(R')/(M-1),
+ *     in FP64; (R')^+ = (R' + s b b^H)^{-1} - b b^H / s with s the power of
+ *     two within a factor of two of tr(R')/(M-1),
  *     the inverse by an FP64 LDL^H factorisation (M <= 4) or Gauss-Jordan
  *     elimination (M >= 5), both without pivoting (the matrix is HPD);
  *   - per bin, in FP64 from the complex64 x, then stored as float:

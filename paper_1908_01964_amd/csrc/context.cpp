@@ -1075,6 +1075,8 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
       A.lin_a0 = r0.a_off;
       A.lin_rp0 = r0.rp_off;
     }
+    // one class alone on the device: its rows share CUs only with each other
+    A.fair = ncls == 1 && fused_fair(cl.M, cl.nt, cl.bpl, cl.count, c->device) ? 1 : 0;
     launch_fused(st, cl.M, cl.nt, cl.bpl, cl.count, A);
     RCSCM_HIP(c, hipGetLastError());
   }

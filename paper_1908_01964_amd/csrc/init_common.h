@@ -7,7 +7,8 @@
 //   2. null check ||R' b|| <= 1e-6 ||R'||_F (b spans the null space of the
 //      rank-(M-1) SCM, Sec. II-B-1);
 //   3. R' <- P R' P, P = I - b b^H, Hermitised (removes the rounding in R'b);
-//   4. A = R' + s b b^H with s = tr(R')/(M-1) is Hermitian positive definite
+//   4. A = R' + s b b^H, s the power of two within a factor of two of
+//      tr(R')/(M-1) (so s b b^H and b b^H / s are exact), is Hermitian positive definite
 //      and, because R' b = 0 and ||b|| = 1, A^{-1} = (R')^+ + b b^H / s -
 //      the pseudoinverse expansion of eq. (26) with lambda = s.  A^{-1} comes
 //      from an LDL^H factorisation in registers for M <= 4, else from a
@@ -132,7 +133,14 @@ __device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
   const double be = s1[6] * inb2;                     // b^H R' b
   if (!(s1[7] * inb2 <= 1e-12 * nr2)) f |= ST_NOT_NULL;  // ||R' b|| <= 1e-6 ||R'||_F
   const double tr = s1[5] - be;                       // tr P R' P
-  const double sh = tr > 0.0 ? tr / (double)(M - 1) : 1.0;
+  // s: a power of two within a factor of two of tr / (M - 1), so that s b b^H
+  // and b b^H / s are exact and no division is needed
+  double sh = 1.0, ish = 1.0;
+  if (tr > 0.0) {
+    const int e = ilogb(tr * (1.0 / (double)(M - 1)));
+    sh = ldexp(1.0, e);
+    ish = ldexp(1.0, -e);
+  }
   wave_sync();
   double2 rhm = make_double2(0.0, 0.0), bb = rhm, ai = rhm, aj = rhm;
   if (ent) {
@@ -160,14 +168,12 @@ __device__ void row_setup_wave(const SetupIn& in, SetupLDS<M>& L) {
     double2 ainv;
     pd = ldl_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + sh), &pivprod, &ainv);
     if (ent) {
-      const double ish = 1.0 / sh;
       q = make_double2(ainv.x - bb.x * ish, ainv.y - bb.y * ish);
       L.sQ[i][j] = q;
     }
   } else {  // (R')^+ = A^{-1} - b b^H / s, Hermitised
     pd = gj_inverse_hpd_wave<M>(L.aug, 1e-13 * (tr + sh), &pivprod);
     if (ent) {
-      const double ish = 1.0 / sh;
       const double2 u = L.aug[i][M + j], v = L.aug[j][M + i];
       q = make_double2(0.5 * (u.x + v.x) - bb.x * ish, 0.5 * (u.y - v.y) - bb.y * ish);
       L.sQ[i][j] = q;

@@ -171,6 +171,8 @@ extern "C" rcscm_status rcscm_run_noalloc(int I, int J, int M, const rcscm_param
   A.K = K;
   A.n_bins = (long long)I * J;
   A.n_rows = I;
+  int dev = -1;
+  A.fair = hipGetDevice(&dev) == hipSuccess && fused_fair(M, nt, bpl, I, dev) ? 1 : 0;
   launch_fused(st, M, nt, bpl, I, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RCSCM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));

@@ -62,7 +62,7 @@ struct RowConstD {
   double2 s_ab;            // a^H b
   double t_aa;             // a^H (R')^+ a
   double det_a;            // det(R' + s b b^H); pdet(R') = det_a / s
-  double shift;            // s = tr(R') / (M - 1)
+  double shift;            // s: the power of two within a factor 2 of tr(R') / (M - 1)
 };
 
 // Float spatial model for the naive rule: a, b and the projected R'.
@@ -155,10 +155,17 @@ struct FusedArgs {
   int K;
   long long n_bins;  // extent of the per-bin arrays (bounds checks of a debug build)
   int n_rows;        // extent of the per-row arrays
+  // Every row of the launch is resident at once: a row's waves lower their
+  // issue priority as the row advances, so that rows sharing a CU progress
+  // together (fused_fair).
+  int fair;
 };
 bool fused_class(int J, int* nt, int* bpl);
 bool fused_supported(int nt, int bpl);
 void launch_fused(hipStream_t s, int M, int nt, int bpl, int nrows, const FusedArgs& A);
+// Whether a launch of nrows rows of one (M, nt, bpl) class on the given device
+// holds all its rows at once (the class's workgroups per CU times the CU count).
+bool fused_fair(int M, int nt, int bpl, int nrows, int device);
 
 // RESIDENT schedule: rows in row_list (all with J <= nt * bpl).
 bool resident_supported(int nt, int bpl);

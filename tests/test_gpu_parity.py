@@ -399,11 +399,15 @@ def test_fused_run_class_boundaries(J):
     assert_close(out[0], ref, what=f"fused J={J}")
 
 
-def test_fused_run_equals_separate_calls(c0):
-    """Same per-bin code and reduction order as init + iterate + extract with 256-lane rows."""
-    out_f, ctx, _ = _gpu_run_fused(c0, 20)
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 20])
+def test_fused_run_equals_separate_calls(c0, K):
+    """Same per-bin code and reduction order as init + iterate + extract with 256-lane rows.  The
+    fused launch runs its K iterations in four segments (its rows are all resident at once, so its
+    waves step their priority down between segments), the RESIDENT kernel as one loop: K below 4
+    and K not divisible by 4 leave segments empty or uneven."""
+    out_f, ctx, _ = _gpu_run_fused(c0, K)
     ctx.close()
-    out_s = gpu_run(c0, 20, schedule="resident", block=256)
+    out_s = gpu_run(c0, K, schedule="resident", block=256)
     for k in ("rh", "ru", "lam", "s_hat"):
         assert np.array_equal(out_f[0][k], out_s[0][k]), k
 
