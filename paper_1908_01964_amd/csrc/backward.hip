@@ -28,6 +28,8 @@
 // At the end x_bar = c tau_bar' + b sigma_bar + 2 nu_bar (R')^+ x with
 // c = (R')^+ a and tau_bar' = tau_bar - 2 tau^ax nu_bar / tau^aa (nu =
 // tau^xx - |tau^ax|^2/tau^aa), in FP64 from the row constants.
+#include <atomic>
+
 #include "accel_common.h"
 
 namespace rcscm {
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
     const float* __restrict__ ck_lam, long long sb, int sr, const float* __restrict__ rh_fin,
     const float* __restrict__ ru_fin, const float* __restrict__ lam_fin, int K, float inv_a2,
     const float2* __restrict__ grad_s, float2* __restrict__ grad_x, float* __restrict__ grad_rh0,
-    float* __restrict__ grad_lam0) {
+    float* __restrict__ grad_lam0, int fair) {
   const int row = row_list[blockIdx.x];
   const RowInfo ri = rows[row];
   const RowConstF rc = rcf[row];
@@ -189,122 +191,139 @@ __global__ __launch_bounds__(NT, (BPL <= 4 ? 4 : 1)) void backward_kernel(
       nu_[q] = on ? ck_ru[(long long)(K - 1) * sb + base + j] : 1.f;
     }
   }
-  for (int k = K - 1; k >= 0; --k) {
-    const float lam = ck_lam[(long long)k * sr + row];
-    const float lam_n = (k + 1 < K) ? ck_lam[(long long)(k + 1) * sr + row] : lam_fin[row];
-    const float il = frcp_nr(lam), il_n = frcp_nr(lam_n);
-    const float A = fmaf(S2, il, taa), A_n = fmaf(S2, il_n, taa);
-    const float sil = sab * il;
-    float vh[BPL], vu[BPL];
-#pragma unroll
-    for (int q = 0; q < BPL; ++q) {
-      vh[q] = nh[q];
-      vu[q] = nu_[q];
+  // As in the forward loop: where all rows of the launch are resident at once
+  // (fair), the 256-lane classes run the reversed iterations in four segments
+  // and lower the waves' priority from one to the next, so that rows sharing
+  // a CU progress together; other classes run one plain loop.
+  constexpr int kSeg = (NT == 256 && BPL <= 4) ? 4 : 1;
+  int k = K - 1;
+  for (int seg = 0; seg < kSeg; ++seg) {
+    if constexpr (kSeg == 4) {
+      if (fair) {
+        if (seg == 0) __builtin_amdgcn_s_setprio(3);
+        if (seg == 1) __builtin_amdgcn_s_setprio(2);
+        if (seg == 2) __builtin_amdgcn_s_setprio(1);
+        if (seg == 3) __builtin_amdgcn_s_setprio(0);
+      }
     }
-    if (k > 0) {  // prefetch theta_{k-1}
+    const int kend = K - ((seg + 1) * K) / kSeg;  // this segment ends at iteration kend
+    for (; k >= kend; --k) {
+      const float lam = ck_lam[(long long)k * sr + row];
+      const float lam_n = (k + 1 < K) ? ck_lam[(long long)(k + 1) * sr + row] : lam_fin[row];
+      const float il = frcp_nr(lam), il_n = frcp_nr(lam_n);
+      const float A = fmaf(S2, il, taa), A_n = fmaf(S2, il_n, taa);
+      const float sil = sab * il;
+      float vh[BPL], vu[BPL];
+#pragma unroll
+      for (int q = 0; q < BPL; ++q) {
+        vh[q] = nh[q];
+        vu[q] = nu_[q];
+      }
+      if (k > 0) {  // prefetch theta_{k-1}
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+          const int j = t + q * NT;
+          const bool on = j < J;
+          nh[q] = on ? ck_rh[(long long)(k - 1) * sb + base + j] : 1.f;
+          nu_[q] = on ? ck_ru[(long long)(k - 1) * sb + base + j] : 1.f;
+        }
+      }
+      // phase-A quantities of iteration k kept for the second pass (the cheap
+      // ones are recomputed there)
+      constexpr bool kKeep = BPL <= 4;  // registers allow it up to 4 bins per lane
+      float viD[BPL], vg[BPL], vE[BPL];
+      float c1 = 0.0f;  // the lane's terms in float
 #pragma unroll
       for (int q = 0; q < BPL; ++q) {
         const int j = t + q * NT;
-        const bool on = j < J;
-        nh[q] = on ? ck_rh[(long long)(k - 1) * sb + base + j] : 1.f;
-        nu_[q] = on ? ck_ru[(long long)(k - 1) * sb + base + j] : 1.f;
+        const float4 T = ts[q];
+        const float h = vh[q], u = vu[q];
+        const float Pr = fmaf(sil, T.z, T.x);
+        const float Pi = fmaf(sil, T.w, T.y);
+        const float iD = frcp(fmaf(h, A, u));
+        const float g = h * iD;
+        const float wr = g * Pr, wi = g * Pi;
+        const float er = fmaf(-sab, wr, T.z), ei = fmaf(-sab, wi, T.w);
+        const float E = fmaf(er, er, ei * ei);
+        if constexpr (kKeep) {
+          viD[q] = iD;
+          vg[q] = g;
+          vE[q] = E;
+        }
+        if (j < J) c1 += ub[q] * invM * fmaf(S2, g * u, E);
       }
-    }
-    // phase-A quantities of iteration k kept for the second pass (the cheap
-    // ones are recomputed there)
-    constexpr bool kKeep = BPL <= 4;  // registers allow it up to 4 bins per lane
-    float viD[BPL], vg[BPL], vE[BPL];
-    float c1 = 0.0f;  // the lane's terms in float
-#pragma unroll
-    for (int q = 0; q < BPL; ++q) {
-      const int j = t + q * NT;
-      const float4 T = ts[q];
-      const float h = vh[q], u = vu[q];
-      const float Pr = fmaf(sil, T.z, T.x);
-      const float Pi = fmaf(sil, T.w, T.y);
-      const float iD = frcp(fmaf(h, A, u));
-      const float g = h * iD;
-      const float wr = g * Pr, wi = g * Pi;
-      const float er = fmaf(-sab, wr, T.z), ei = fmaf(-sab, wi, T.w);
-      const float E = fmaf(er, er, ei * ei);
-      if constexpr (kKeep) {
-        viD[q] = iD;
-        vg[q] = g;
-        vE[q] = E;
-      }
-      if (j < J) c1 += ub[q] * invM * fmaf(S2, g * u, E);
-    }
-    const double ilnbar = block_sum_f32<NT>(c1, red, phase);
-    const float lam_n_bar = (float)((double)lam_bar - (double)il_n * (double)il_n * ilnbar);
-    const float tbar = lam_n_bar * rc.invJ;
+      const double ilnbar = block_sum_f32<NT>(c1, red, phase);
+      const float lam_n_bar = (float)((double)lam_bar - (double)il_n * (double)il_n * ilnbar);
+      const float tbar = lam_n_bar * rc.invJ;
 
-    float c2 = 0.0f;
+      float c2 = 0.0f;
 #pragma unroll
-    for (int q = 0; q < BPL; ++q) {
-      const int j = t + q * NT;
-      const float4 T = ts[q];
-      const float h = vh[q], u = vu[q];
-      const float Pr = fmaf(sil, T.z, T.x);
-      const float Pi = fmaf(sil, T.w, T.y);
-      const float iD = kKeep ? viD[q] : frcp(fmaf(h, A, u));
-      const float g = kKeep ? vg[q] : h * iD;
-      const float iu = frcp(u);
-      const float R2 = Pr * Pr + Pi * Pi;
-      const float Q = fmaf(g, R2, u);
-      const float wr = g * Pr, wi = g * Pi;
-      const float er = fmaf(-sab, wr, T.z), ei = fmaf(-sab, wi, T.w);
-      const float E = kKeep ? vE[q] : fmaf(er, er, ei * ei);
-      const float dr = T.x - wr * taa, di = T.y - wi * taa;
-      // r^u_{k+1} = (g u A_n + nu + |d|^2 / taa + E / lambda_n) / M
-      const float uu = ub[q] * invM;
-      float gbar = uu * u * A_n;
-      float ubar = uu * g * A_n;
-      nub[q] += uu;
-      const float dsc = 2.0f * uu * rc.inv_t_aa;
-      const float dbr = dsc * dr, dbi = dsc * di;
-      float Ebar = uu * il_n;
-      // lambda_{k+1} = mean_j (g S2 + E / u)
-      gbar += S2 * tbar;
-      Ebar += tbar * iu;
-      ubar -= E * iu * iu * tbar;
-      // d = T - w taa
-      Tbr[q] += dbr;
-      Tbi[q] += dbi;
-      float wbr = -taa * dbr, wbi = -taa * dbi;
-      // E = |e|^2 ; p e = U - |s| w
-      const float ebr = 2.0f * er * Ebar, ebi = 2.0f * ei * Ebar;
-      Bbr[q] += ebr;
-      Bbi[q] += ebi;
-      wbr = fmaf(-sab, ebr, wbr);
-      wbi = fmaf(-sab, ebi, wbi);
-      // w = g P
-      gbar += Pr * wbr + Pi * wbi;
-      float Pbr = g * wbr, Pbi = g * wbi;
-      // h_{k+1} = g Q / (alpha + 2) + beta / (alpha + 2)
-      const float hp = hb[q] * inv_a2;
-      gbar += hp * Q;
-      const float Qbar = hp * g;
-      // Q = u + g R2 ; R2 = |P|^2
-      ubar += Qbar;
-      gbar += Qbar * R2;
-      Pbr += 2.0f * Pr * (Qbar * g);
-      Pbi += 2.0f * Pi * (Qbar * g);
-      // g = h / D ; D = u + h A
-      float hbar = gbar * iD;
-      const float Dbar = -gbar * g * iD;
-      ubar += Dbar;
-      hbar += Dbar * A;
-      // P = T + |s| il U
-      Tbr[q] += Pbr;
-      Tbi[q] += Pbi;
-      Bbr[q] = fmaf(sil, Pbr, Bbr[q]);
-      Bbi[q] = fmaf(sil, Pbi, Bbi[q]);
-      if (j < J) c2 += fmaf(sab, fmaf(T.z, Pbr, T.w * Pbi), S2 * Dbar * h);
-      hb[q] = hbar;
-      ub[q] = ubar;
+      for (int q = 0; q < BPL; ++q) {
+        const int j = t + q * NT;
+        const float4 T = ts[q];
+        const float h = vh[q], u = vu[q];
+        const float Pr = fmaf(sil, T.z, T.x);
+        const float Pi = fmaf(sil, T.w, T.y);
+        const float iD = kKeep ? viD[q] : frcp(fmaf(h, A, u));
+        const float g = kKeep ? vg[q] : h * iD;
+        const float iu = frcp(u);
+        const float R2 = Pr * Pr + Pi * Pi;
+        const float Q = fmaf(g, R2, u);
+        const float wr = g * Pr, wi = g * Pi;
+        const float er = fmaf(-sab, wr, T.z), ei = fmaf(-sab, wi, T.w);
+        const float E = kKeep ? vE[q] : fmaf(er, er, ei * ei);
+        const float dr = T.x - wr * taa, di = T.y - wi * taa;
+        // r^u_{k+1} = (g u A_n + nu + |d|^2 / taa + E / lambda_n) / M
+        const float uu = ub[q] * invM;
+        float gbar = uu * u * A_n;
+        float ubar = uu * g * A_n;
+        nub[q] += uu;
+        const float dsc = 2.0f * uu * rc.inv_t_aa;
+        const float dbr = dsc * dr, dbi = dsc * di;
+        float Ebar = uu * il_n;
+        // lambda_{k+1} = mean_j (g S2 + E / u)
+        gbar += S2 * tbar;
+        Ebar += tbar * iu;
+        ubar -= E * iu * iu * tbar;
+        // d = T - w taa
+        Tbr[q] += dbr;
+        Tbi[q] += dbi;
+        float wbr = -taa * dbr, wbi = -taa * dbi;
+        // E = |e|^2 ; p e = U - |s| w
+        const float ebr = 2.0f * er * Ebar, ebi = 2.0f * ei * Ebar;
+        Bbr[q] += ebr;
+        Bbi[q] += ebi;
+        wbr = fmaf(-sab, ebr, wbr);
+        wbi = fmaf(-sab, ebi, wbi);
+        // w = g P
+        gbar += Pr * wbr + Pi * wbi;
+        float Pbr = g * wbr, Pbi = g * wbi;
+        // h_{k+1} = g Q / (alpha + 2) + beta / (alpha + 2)
+        const float hp = hb[q] * inv_a2;
+        gbar += hp * Q;
+        const float Qbar = hp * g;
+        // Q = u + g R2 ; R2 = |P|^2
+        ubar += Qbar;
+        gbar += Qbar * R2;
+        Pbr += 2.0f * Pr * (Qbar * g);
+        Pbi += 2.0f * Pi * (Qbar * g);
+        // g = h / D ; D = u + h A
+        float hbar = gbar * iD;
+        const float Dbar = -gbar * g * iD;
+        ubar += Dbar;
+        hbar += Dbar * A;
+        // P = T + |s| il U
+        Tbr[q] += Pbr;
+        Tbi[q] += Pbi;
+        Bbr[q] = fmaf(sil, Pbr, Bbr[q]);
+        Bbi[q] = fmaf(sil, Pbi, Bbi[q]);
+        if (j < J) c2 += fmaf(sab, fmaf(T.z, Pbr, T.w * Pbi), S2 * Dbar * h);
+        hb[q] = hbar;
+        ub[q] = ubar;
+      }
+      const double ilbar = block_sum_f32<NT>(c2, red, phase);
+      lam_bar = (float)(-(double)il * (double)il * ilbar);
     }
-    const double ilbar = block_sum_f32<NT>(c2, red, phase);
-    lam_bar = (float)(-(double)il * (double)il * ilbar);
   }
 
   if (t == 0 && grad_lam0 != nullptr) grad_lam0[row] = lam_bar;
@@ -367,16 +386,26 @@ void bw_launch(hipStream_t s, int nrows, const int* row_list, const RowInfo* row
                const float* nu, const float* ck_rh, const float* ck_ru, const float* ck_lam,
                long long sb, int sr, const float* rh_fin, const float* ru_fin,
                const float* lam_fin, int K, float inv_a2, const float2* grad_s, float2* grad_x,
-               float* grad_rh0, float* grad_lam0) {
+               float* grad_rh0, float* grad_lam0, int fair) {
   hipLaunchKernelGGL((backward_kernel<NT, BPL>), dim3(nrows), dim3(NT), 0, s, row_list, rows, rcf,
                      rcd, x, tsig, nu, ck_rh, ck_ru, ck_lam, sb, sr, rh_fin, ru_fin, lam_fin, K,
-                     inv_a2, grad_s, grad_x, grad_rh0, grad_lam0);
+                     inv_a2, grad_s, grad_x, grad_rh0, grad_lam0, fair);
+}
+
+// Workgroups of backward_kernel<NT, BPL> one CU holds at once (0 if unknown).
+template <int NT, int BPL>
+int bw_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, backward_kernel<NT, BPL>, NT, 0) !=
+      hipSuccess)
+    n = 0;
+  return n;
 }
 
 using BwFn = void (*)(hipStream_t, int, const int*, const RowInfo*, const RowConstF*,
                       const RowConstD*, const float2*, const float4*, const float*, const float*,
                       const float*, const float*, long long, int, const float*, const float*,
-                      const float*, int, float, const float2*, float2*, float*, float*);
+                      const float*, int, float, const float2*, float2*, float*, float*, int);
 
 #define RCSCM_BW_LIST(NT)                                                                   \
   {bw_launch<NT, 1>, bw_launch<NT, 2>, bw_launch<NT, 3>, bw_launch<NT, 4>, bw_launch<NT, 5>, \
@@ -390,7 +419,37 @@ using BwFn = void (*)(hipStream_t, int, const int*, const RowInfo*, const RowCon
 const BwFn kBw[5][16] = {RCSCM_BW_LIST(64), RCSCM_BW_LIST(128), RCSCM_BW_LIST(256),
                          RCSCM_BW_LIST(512), RCSCM_BW_LIST_1024};
 
+int bw_class_index(int nt) {
+  switch (nt) {
+    case 64: return 0;
+    case 128: return 1;
+    case 256: return 2;
+    case 512: return 3;
+    case 1024: return 4;
+    default: return -1;
+  }
+}
+
 }  // namespace
+
+bool backward_fair(int nt, int bpl, int nrows, int device) {
+  if (nt != 256 || bpl < 1 || bpl > 4) return false;  // only these classes have the steps
+  static std::atomic<int> cache[4];                   // per bpl; 0 = not yet queried
+  int v = cache[bpl - 1].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int n = 0;
+    switch (bpl) {
+      case 1: n = bw_blocks_per_cu<256, 1>(); break;
+      case 2: n = bw_blocks_per_cu<256, 2>(); break;
+      case 3: n = bw_blocks_per_cu<256, 3>(); break;
+      case 4: n = bw_blocks_per_cu<256, 4>(); break;
+      default: break;
+    }
+    v = n > 0 ? n : -1;
+    cache[bpl - 1].store(v, std::memory_order_relaxed);
+  }
+  return v > 0 && (long long)nrows <= (long long)v * device_cu_count(device);
+}
 
 void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_list,
                      const RowInfo* rows, const RowConstF* rcf, const RowConstD* rcd,
@@ -398,22 +457,14 @@ void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_l
                      const float* ckpt_ru, const float* ckpt_lam, long long ckpt_stride_bins,
                      int ckpt_stride_rows, const float* rh_fin, const float* ru_fin,
                      const float* lam_fin, int K, float alpha, const float2* grad_s,
-                     float2* grad_x, float* grad_rh0, float* grad_lam0) {
+                     float2* grad_x, float* grad_rh0, float* grad_lam0, int fair) {
   if (nrows <= 0) return;
-  int ni = -1;
-  switch (nt) {
-    case 64: ni = 0; break;
-    case 128: ni = 1; break;
-    case 256: ni = 2; break;
-    case 512: ni = 3; break;
-    case 1024: ni = 4; break;
-    default: return;
-  }
-  if (bpl < 1 || bpl > 16 || kBw[ni][bpl - 1] == nullptr) return;
+  const int ni = bw_class_index(nt);
+  if (ni < 0 || bpl < 1 || bpl > 16 || kBw[ni][bpl - 1] == nullptr) return;
   const float inv_a2 = (float)(1.0 / ((double)alpha + 2.0));
   kBw[ni][bpl - 1](s, nrows, row_list, rows, rcf, rcd, x, tsig, nu, ckpt_rh, ckpt_ru, ckpt_lam,
                    ckpt_stride_bins, ckpt_stride_rows, rh_fin, ru_fin, lam_fin, K, inv_a2, grad_s,
-                   grad_x, grad_rh0, grad_lam0);
+                   grad_x, grad_rh0, grad_lam0, fair);
 }
 
 }  // namespace rcscm

@@ -902,12 +902,15 @@ rcscm_status rcscm_backward(rcscm_ctx* c, const void* x, const void* grad_s_hat,
     return c->fail(RCSCM_ESTATE, "backward needs a context with checkpoints that was iterated");
   if (!x || !grad_s_hat) return c->fail(RCSCM_EINVAL, "x and grad_s_hat must not be NULL");
   for (const auto& cl : c->res_classes) {
+    // one class: its rows share CUs only with each other
+    const int fair = c->res_classes.size() == 1 &&
+                     backward_fair(cl.nt, cl.bpl, cl.count, c->device);
     launch_backward(c->stream, cl.nt, cl.bpl, cl.count, c->d_row_list + cl.offset, c->d_rows,
                     c->d_rcf, c->d_rcd, static_cast<const float2*>(x), c->d_tsig, c->d_nu,
                     c->d_ck_rh, c->d_ck_ru, c->d_ck_lam, c->nbins, c->nrows, c->d_rh, c->d_ru,
                     c->d_lam[c->lam_cur], c->ck_K, (float)c->p.alpha,
                     static_cast<const float2*>(grad_s_hat), static_cast<float2*>(grad_x),
-                    grad_rh0, grad_lam0);
+                    grad_rh0, grad_lam0, fair);
     RCSCM_HIP(c, hipGetLastError());
   }
   return RCSCM_OK;

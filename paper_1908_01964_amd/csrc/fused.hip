@@ -237,18 +237,22 @@ int fused_blocks_per_cu(int M, int nt, int bpl) {
 // same steps lengthened it by about 4 % (a row that finishes early frees its
 // CU for the next), so they are left off there.
 bool fused_fair(int M, int nt, int bpl, int nrows, int device) {
+  const int per_cu = fused_blocks_per_cu(M, nt, bpl);
+  return per_cu > 0 && (long long)nrows <= (long long)per_cu * device_cu_count(device);
+}
+
+int device_cu_count(int device) {
   static std::atomic<int> cus[64];  // CU count per device; 0 = not yet queried
-  if (device < 0 || device >= 64) return false;
+  if (device < 0 || device >= 64) return 0;
   int ncu = cus[device].load(std::memory_order_relaxed);
   if (ncu == 0) {
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) !=
             hipSuccess ||
         ncu <= 0)
-      return false;
+      return 0;
     cus[device].store(ncu, std::memory_order_relaxed);
   }
-  const int per_cu = fused_blocks_per_cu(M, nt, bpl);
-  return per_cu > 0 && (long long)nrows <= (long long)per_cu * ncu;
+  return ncu;
 }
 
 void launch_fused(hipStream_t s, int M, int nt, int bpl, int nrows, const FusedArgs& A) {

@@ -166,6 +166,8 @@ void launch_fused(hipStream_t s, int M, int nt, int bpl, int nrows, const FusedA
 // Whether a launch of nrows rows of one (M, nt, bpl) class on the given device
 // holds all its rows at once (the class's workgroups per CU times the CU count).
 bool fused_fair(int M, int nt, int bpl, int nrows, int device);
+// Compute units of a device (0 if the query fails), queried once per device.
+int device_cu_count(int device);
 
 // RESIDENT schedule: rows in row_list (all with J <= nt * bpl).
 bool resident_supported(int nt, int bpl);
@@ -241,6 +243,9 @@ void launch_backward(hipStream_t s, int nt, int bpl, int nrows, const int* row_l
                      const float* ckpt_ru, const float* ckpt_lam, long long ckpt_stride_bins,
                      int ckpt_stride_rows, const float* rh_fin, const float* ru_fin,
                      const float* lam_fin, int K, float alpha, const float2* grad_s,
-                     float2* grad_x, float* grad_rh0, float* grad_lam0);
+                     float2* grad_x, float* grad_rh0, float* grad_lam0, int fair);
+// Whether a backward launch of nrows rows of one (nt, bpl) class holds all its
+// rows at once on the device (as fused_fair).
+bool backward_fair(int nt, int bpl, int nrows, int device);
 
 }  // namespace rcscm
