@@ -17,6 +17,8 @@
 //   iteration k-1 is recomputed from the stored state of iteration k-2
 //   (cheap arithmetic) instead of storing its intermediates.  HBM traffic
 //   per launch: 28 bytes read and 8 bytes written per bin.
+#include <atomic>
+
 #include "resident_loop.h"
 #include "xcd_order.h"
 
@@ -26,6 +28,11 @@ namespace {
 
 // ---------------------------------------------------------------- RESIDENT --
 
+// The classes that compile the priority steps of the loop (resident_segments):
+// 256 lanes, up to four bins per lane.
+template <int NT, int BPL>
+constexpr bool kResFairClass = NT == 256 && BPL <= 4;
+
 template <int NT, int BPL, int LS>
 __global__ __launch_bounds__(NT) void accel_resident_kernel(
     const int* __restrict__ row_list, const RowInfo* __restrict__ rows,
@@ -33,7 +40,7 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
     const float* __restrict__ nu, float* __restrict__ rh, float* __restrict__ ru,
     float* __restrict__ lam, float inv_a2, float beta_a2, int K, float* __restrict__ ck_rh,
     float* __restrict__ ck_ru, float* __restrict__ ck_lam, long long ck_sb, int ck_sr,
-    unsigned* __restrict__ status) {
+    unsigned* __restrict__ status, int fair) {
   constexpr int NW = NT / 64;
   const int row = row_list[blockIdx.x];
   const RowInfo ri = rows[row];
@@ -62,9 +69,9 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
     }
   }
   __shared__ uint64_t red[2][NW];
-  const float lam_t = resident_iterations<NT, BPL, LS, false>(ts, vnu, vrh, vru, rc, lam[row], row, J,
+  const float lam_t = resident_iterations<NT, BPL, LS, kResFairClass<NT, BPL>>(ts, vnu, vrh, vru, rc, lam[row], row, J,
                                                        base, K, inv_a2, beta_a2, red, ck_rh,
-                                                       ck_ru, ck_lam, ck_sb, ck_sr, false);
+                                                       ck_ru, ck_lam, ck_sb, ck_sr, fair != 0);
 
   bool bad = false;
 #pragma unroll
@@ -87,15 +94,25 @@ template <int NT, int BPL, int LS>
 void res_launch(hipStream_t s, int nrows, const int* row_list, const RowInfo* rows,
                 const RowConstF* rcf, const float4* tsig, const float* nu, float* rh, float* ru,
                 float* lam, float inv_a2, float beta_a2, int K, float* ck_rh, float* ck_ru,
-                float* ck_lam, long long ck_sb, int ck_sr, unsigned* status) {
+                float* ck_lam, long long ck_sb, int ck_sr, unsigned* status, int fair) {
   hipLaunchKernelGGL((accel_resident_kernel<NT, BPL, LS>), dim3(nrows), dim3(NT), 0, s, row_list,
                      rows, rcf, tsig, nu, rh, ru, lam, inv_a2, beta_a2, K, ck_rh, ck_ru, ck_lam,
-                     ck_sb, ck_sr, status);
+                     ck_sb, ck_sr, status, fair);
+}
+
+// Workgroups of accel_resident_kernel<NT, BPL, LS> one CU holds at once (0 if unknown).
+template <int NT, int BPL, int LS>
+int res_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, accel_resident_kernel<NT, BPL, LS>, NT,
+                                                   0) != hipSuccess)
+    n = 0;
+  return n;
 }
 
 using ResFn = void (*)(hipStream_t, int, const int*, const RowInfo*, const RowConstF*,
                        const float4*, const float*, float*, float*, float*, float, float, int,
-                       float*, float*, float*, long long, int, unsigned*);
+                       float*, float*, float*, long long, int, unsigned*, int);
 
 #define RCSCM_RES_BPL_LIST(NT, LS)                                                       \
   {res_launch<NT, 1, LS>, res_launch<NT, 2, LS>, res_launch<NT, 3, LS>,                  \
@@ -365,14 +382,38 @@ void launch_accel_resident(hipStream_t s, int nt, int bpl, int lamsum, int nrows
                            const float4* tsig, const float* nu, float* rh, float* ru, float* lam,
                            float alpha, float beta, int K, float* ckpt_rh, float* ckpt_ru,
                            float* ckpt_lam, long long ckpt_stride_bins, int ckpt_stride_rows,
-                           unsigned* status) {
+                           unsigned* status, int fair) {
   if (nrows <= 0 || K <= 0) return;
   const float inv_a2 = (float)(1.0 / ((double)alpha + 2.0));
   const float beta_a2 = (float)((double)beta / ((double)alpha + 2.0));
   kRes[lamsum ? 1 : 0][nt_index(nt)][bpl - 1](s, nrows, row_list, rows, rcf, tsig, nu, rh, ru,
                                               lam, inv_a2, beta_a2, K, ckpt_rh, ckpt_ru,
                                               ckpt_lam, ckpt_stride_bins, ckpt_stride_rows,
-                                              status);
+                                              status, fair);
+}
+
+bool resident_fair(int nt, int bpl, int lamsum, int nrows, int device) {
+  if (nt != 256 || bpl < 1 || bpl > 4) return false;  // only these classes have the steps
+  static std::atomic<int> cache[2][4];                // per (policy, bpl); 0 = not yet queried
+  const int ls = lamsum ? 1 : 0;
+  int v = cache[ls][bpl - 1].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int n = 0;
+    switch (bpl * 2 + ls) {
+      case 2: n = res_blocks_per_cu<256, 1, 0>(); break;
+      case 3: n = res_blocks_per_cu<256, 1, 1>(); break;
+      case 4: n = res_blocks_per_cu<256, 2, 0>(); break;
+      case 5: n = res_blocks_per_cu<256, 2, 1>(); break;
+      case 6: n = res_blocks_per_cu<256, 3, 0>(); break;
+      case 7: n = res_blocks_per_cu<256, 3, 1>(); break;
+      case 8: n = res_blocks_per_cu<256, 4, 0>(); break;
+      case 9: n = res_blocks_per_cu<256, 4, 1>(); break;
+      default: break;
+    }
+    v = n > 0 ? n : -1;
+    cache[ls][bpl - 1].store(v, std::memory_order_relaxed);
+  }
+  return v > 0 && (long long)nrows <= (long long)v * device_cu_count(device);
 }
 
 void launch_accel_stream(hipStream_t s, int lamsum, bool finish_prev, bool start_next,

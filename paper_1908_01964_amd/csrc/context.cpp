@@ -762,10 +762,13 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
       c->ck_K = K;
     }
     for (const auto& cl : c->res_classes) {
+      // one class: its rows share CUs only with each other
+      const int fair = c->res_classes.size() == 1 &&
+                       resident_fair(cl.nt, cl.bpl, c->p.lamsum, cl.count, c->device);
       launch_accel_resident(s, cl.nt, cl.bpl, c->p.lamsum, cl.count, c->d_row_list + cl.offset,
                             c->d_rows, c->d_rcf, c->d_tsig, c->d_nu, c->d_rh, c->d_ru,
                             c->d_lam[c->lam_cur], alpha, beta, K, ck_rh, ck_ru, ck_lam, c->nbins,
-                            c->nrows, c->d_status);
+                            c->nrows, c->d_status, fair);
       RCSCM_HIP(c, hipGetLastError());
     }
     return RCSCM_OK;

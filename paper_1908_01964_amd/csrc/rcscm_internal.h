@@ -176,7 +176,11 @@ void launch_accel_resident(hipStream_t s, int nt, int bpl, int lamsum, int nrows
                            const float4* tsig, const float* nu, float* rh, float* ru, float* lam,
                            float alpha, float beta, int K, float* ckpt_rh, float* ckpt_ru,
                            float* ckpt_lam, long long ckpt_stride_bins, int ckpt_stride_rows,
-                           unsigned* status);
+                           unsigned* status, int fair);
+// Whether a RESIDENT launch of nrows rows of one (nt, bpl) class holds all its
+// rows at once on the device (as fused_fair); fair then lowers the waves'
+// priority as a row advances.
+bool resident_fair(int nt, int bpl, int lamsum, int nrows, int device);
 
 // STREAM schedule: one launch of stage (finish iteration k-1, start iteration k).
 // nu_early: request nu with the rest of a bin's state (for state that stays in
