@@ -69,9 +69,9 @@ __global__ __launch_bounds__(NT) void accel_resident_kernel(
     }
   }
   __shared__ uint64_t red[2][NW];
-  const float lam_t = resident_iterations<NT, BPL, LS, kResFairClass<NT, BPL>>(ts, vnu, vrh, vru, rc, lam[row], row, J,
-                                                       base, K, inv_a2, beta_a2, red, ck_rh,
-                                                       ck_ru, ck_lam, ck_sb, ck_sr, fair != 0);
+  const float lam_t = resident_iterations<NT, BPL, LS, kResFairClass<NT, BPL>>(
+      ts, vnu, vrh, vru, rc, lam[row], row, J, base, K, inv_a2, beta_a2, red, ck_rh, ck_ru, ck_lam,
+      ck_sb, ck_sr, fair != 0);
 
   bool bad = false;
 #pragma unroll

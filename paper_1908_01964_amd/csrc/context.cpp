@@ -63,6 +63,9 @@ struct rcscm_ctx {
   std::vector<std::pair<int, int>> mrow_range = std::vector<std::pair<int, int>>(RCSCM_MAX_M + 1, {0, 0});
   struct ResClass {
     int nt, bpl, count, offset;
+    // the class is the only one and all its rows are resident at once: the RESIDENT and the
+    // backward launch lower their waves' priority as a row advances (set_fair_flags)
+    bool fair_res = false, fair_bw = false;
   };
   std::vector<ResClass> res_classes;
   std::vector<ResClass> first_classes;  // FIRST rule: nt field holds M
@@ -70,6 +73,7 @@ struct rcscm_ctx {
     int M, nt, bpl, count, offset;
     bool linear;  // consecutive rows of one utterance (offsets linear in the row index)
     int row0;     // first row of the class
+    bool fair = false;  // as ResClass, for the fused launch
   };
   std::vector<FusedClass> fused_classes;  // rcscm_run (empty: not available)
   int fused_offset = 0;                     // the fused classes' part of d_row_list
@@ -363,6 +367,20 @@ static void group_fused(rcscm_ctx* c, std::vector<int>* row_list,
   }
 }
 
+// The priority-step flags of the classes (fused_fair, resident_fair, backward_fair): a class
+// qualifies when it is the only one of its launch kind.  The occupancy queries behind them run
+// here, when the classes are formed, so that no launch (possibly under graph capture) makes them.
+static void set_fair_flags(rcscm_ctx* c) {
+  for (auto& cl : c->res_classes) {
+    cl.fair_res = c->res_classes.size() == 1 &&
+                  resident_fair(cl.nt, cl.bpl, c->p.lamsum, cl.count, c->device);
+    cl.fair_bw = c->res_classes.size() == 1 && backward_fair(cl.nt, cl.bpl, cl.count, c->device);
+  }
+  for (auto& cl : c->fused_classes)
+    cl.fair = c->fused_classes.size() == 1 &&
+              fused_fair(cl.M, cl.nt, cl.bpl, cl.count, c->device);
+}
+
 static rcscm_status build_tables(rcscm_ctx* c) {
   const int U = c->U, I = c->I;
   c->nrows = U * I;
@@ -471,6 +489,7 @@ static rcscm_status build_tables(rcscm_ctx* c) {
   c->fused_offset = (int)row_list.size();
   if (c->p.rule == RCSCM_RULE_ACCEL && maxJ <= kMaxResidentJ)
     group_fused(c, &row_list, &c->fused_classes);
+  set_fair_flags(c);
   if (row_list.empty()) row_list.push_back(0);
   // device copies
   RCSCM_TRY(c->alloc(&c->d_rows, c->nrows, "rows"));
@@ -762,9 +781,7 @@ rcscm_status rcscm_iterate(rcscm_ctx* c, int K) {
       c->ck_K = K;
     }
     for (const auto& cl : c->res_classes) {
-      // one class: its rows share CUs only with each other
-      const int fair = c->res_classes.size() == 1 &&
-                       resident_fair(cl.nt, cl.bpl, c->p.lamsum, cl.count, c->device);
+      const int fair = cl.fair_res ? 1 : 0;
       launch_accel_resident(s, cl.nt, cl.bpl, c->p.lamsum, cl.count, c->d_row_list + cl.offset,
                             c->d_rows, c->d_rcf, c->d_tsig, c->d_nu, c->d_rh, c->d_ru,
                             c->d_lam[c->lam_cur], alpha, beta, K, ck_rh, ck_ru, ck_lam, c->nbins,
@@ -905,9 +922,7 @@ rcscm_status rcscm_backward(rcscm_ctx* c, const void* x, const void* grad_s_hat,
     return c->fail(RCSCM_ESTATE, "backward needs a context with checkpoints that was iterated");
   if (!x || !grad_s_hat) return c->fail(RCSCM_EINVAL, "x and grad_s_hat must not be NULL");
   for (const auto& cl : c->res_classes) {
-    // one class: its rows share CUs only with each other
-    const int fair = c->res_classes.size() == 1 &&
-                     backward_fair(cl.nt, cl.bpl, cl.count, c->device);
+    const int fair = cl.fair_bw ? 1 : 0;
     launch_backward(c->stream, cl.nt, cl.bpl, cl.count, c->d_row_list + cl.offset, c->d_rows,
                     c->d_rcf, c->d_rcd, static_cast<const float2*>(x), c->d_tsig, c->d_nu,
                     c->d_ck_rh, c->d_ck_ru, c->d_ck_lam, c->nbins, c->nrows, c->d_rh, c->d_ru,
@@ -1081,8 +1096,7 @@ rcscm_status rcscm_run(rcscm_ctx* c, const void* x, const void* a, const void* R
       A.lin_a0 = r0.a_off;
       A.lin_rp0 = r0.rp_off;
     }
-    // one class alone on the device: its rows share CUs only with each other
-    A.fair = ncls == 1 && fused_fair(cl.M, cl.nt, cl.bpl, cl.count, c->device) ? 1 : 0;
+    A.fair = cl.fair ? 1 : 0;
     launch_fused(st, cl.M, cl.nt, cl.bpl, cl.count, A);
     RCSCM_HIP(c, hipGetLastError());
   }
@@ -1124,6 +1138,7 @@ rcscm_status rcscm_set_run_classes(rcscm_ctx* c, int n, const int* table) {
   RCSCM_HIP(c, hipMemcpy(c->d_row_list + c->fused_offset, rl.data(), sizeof(int) * rl.size(),
                          hipMemcpyHostToDevice));
   c->fused_classes = cls;
+  set_fair_flags(c);
   return RCSCM_OK;
 }
 
