@@ -62,6 +62,21 @@ def test_config2_batch_equals_single_runs(batch):
             assert np.array_equal(single[k], outs[u][k]), (u, k)
 
 
+def test_config2_fused_batch_equals_single_runs(batch):
+    """rcscm_run over the batch (ten classes on several streams: no priority steps) against the
+    same utterances run alone (one 256-lane class holding all its rows at once: priority steps
+    on; or a 512-lane one: off): the same class kernel, so the results are equal bitwise."""
+    Js, Ms, probs = batch
+    K = 20
+    outs = gpu_run(probs, K, fused=True)
+    short = [u for u in range(len(Js)) if Js[u] <= 2048][:3]
+    long_ = [u for u in range(len(Js)) if Js[u] > 2048][:1]
+    for u in short + long_:
+        single = gpu_run(probs[u], K, fused=True)[0]
+        for k in ("rh", "ru", "lam", "s_hat"):
+            assert np.array_equal(single[k], outs[u][k]), (u, Js[u], k)
+
+
 def test_config4_full_size_subsample():
     """M=8, I=1025, J=8000, K=30; the FP64 oracle checks 64 frequencies incl. DC and Nyquist."""
     p = config(4)
