@@ -104,10 +104,9 @@ __global__ __launch_bounds__(NT) void accel_fused_kernel(const FusedArgs A) {
     if (q + G < BPL) load_bin(q + G, xv[q % G]);
   }
   const float lam0 = A.lam0 ? A.lam0[row] : A.lam_c;
-  const float lam_fin = resident_iterations<NT, BPL, 0, kFairClass>(ts, vnu, vrh, vru, rc, lam0, row, J, base,
-                                                        A.K, A.inv_a2, A.beta_a2, red, A.ck_rh,
-                                                        A.ck_ru, A.ck_lam, A.ck_sb, A.ck_sr,
-                                                        kFairClass && A.fair != 0);
+  const float lam_fin = resident_iterations<NT, BPL, 0, kFairClass>(
+      ts, vnu, vrh, vru, rc, lam0, row, J, base, A.K, A.inv_a2, A.beta_a2, red, A.ck_rh, A.ck_ru,
+      A.ck_lam, A.ck_sb, A.ck_sr, kFairClass && A.fair != 0);
   const LamTerms Lf = lam_terms(rc, lam_fin);
 #pragma unroll
   for (int q = 0; q < BPL; ++q) {
@@ -211,8 +210,8 @@ int fused_blocks_per_cu_m(int nt, int bpl) {
 // the same on every gfx950 device, queried once per class.
 int fused_blocks_per_cu(int M, int nt, int bpl) {
   static std::atomic<int> cache[9][3][9];  // M, log2(nt / 256), bpl; 0 = not yet queried
+  if (M < 2 || M > 8 || bpl < 1 || bpl > 8 || !fused_supported(nt, bpl)) return 0;
   const int ni = nt == 256 ? 0 : (nt == 512 ? 1 : 2);
-  if (M < 2 || M > 8 || bpl < 1 || bpl > 8) return 0;
   int v = cache[M][ni][bpl].load(std::memory_order_relaxed);
   if (v != 0) return v > 0 ? v : 0;
   int n = 0;
