@@ -280,8 +280,12 @@ rcscm_status rcscm_backproject(rcscm_ctx* ctx, const void* x, const void* W, con
  * RCSCM_FLAG_CHECKPOINT, 1 <= J <= 8192, 1 <= I <= RCSCM_NOALLOC_MAX_ROWS.
  * Scratch: one status word per row in a static device array of the library
  * (RCSCM_NOALLOC_MAX_ROWS + 8 words, 256 KiB, per GPU, held until the process
- * ends); calls that overlap on one GPU race on it.  check == 0: the call only
- * enqueues work on the stream (capturable); data errors are not reported.
+ * ends); calls that overlap on one GPU race on it.  The first call on a
+ * device looks up the array's device address, and the first with a given
+ * workgroup class queries the device's CU count and the class's occupancy
+ * (host-side queries, cached for the process; no device work).  check == 0:
+ * the call only enqueues work on the stream (capturable); data errors are not
+ * reported.
  * check != 0: the call also reduces the status words, waits for the stream
  * and returns the first data error as rcscm_sync would (ENONFINITE,
  * ENOTNULL, ENOTPSD), described by rcscm_last_error(NULL). */
